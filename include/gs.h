@@ -1,0 +1,187 @@
+/*
+ * gs.h -- C ABI of the MI355X generalized-sampling library (libgs.so).
+ *
+ * Generalized sampling (Jacobsen, Nielsen, Rasmussen, "Generalized Sampling
+ * in Julia", arXiv 1607.04091): given M Fourier samples y_m of a function on
+ * [-1/2, 1/2]^d at frequencies xi_m, find the coefficients x of its
+ * approximation in V_J^int (boundary-corrected Daubechies scaling functions
+ * with p vanishing moments, N = 2^J functions per dimension, Sec. 3.3) as the
+ * weighted least-squares solution of T x = y (Sec. 2 eq. least_squares,
+ * Sec. 4.1 eq. weighted_least_squares).  T is the M x N^d change-of-basis
+ * matrix of Sec. 4 (1D block form [L I R], eq. CoB_block_1D) and Sec. 5 /
+ * App. C (2D tensor product, eq. 2Dwavelet_border_division).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Frequencies xi are unnormalized (the paper's xi_m); 2D points are stored
+ *   interleaved (xi_x, xi_y) per point.
+ * - Column n (0-based) of the 1D basis is: n < p  -> left boundary function
+ *   phi^L_n shifted to -1/2; p <= n < N-p -> interior phi_{J, n-N/2};
+ *   n >= N-p -> right boundary function phi^R_{N-1-n} shifted to +1/2
+ *   (Sec. 3.3 ordering: phi^L_0 .. phi^L_{p-1}, interior, phi^R_{p-1} .. phi^R_0).
+ *   For Haar (p = 1) every column is interior.
+ * - 2D coefficients are ROW-MAJOR X[i][j], i the x index (fast index j = y).
+ *   This differs from the column-major vec() of App. C.
+ * - Complex vectors are interleaved (re, im): complex128 for FP64 data,
+ *   complex64 for FP32 data.
+ * - Device pointers are HIP device pointers on the current device; the
+ *   caller owns them.  `stream` is a hipStream_t (NULL = default stream).
+ *   Every apply is stream-ordered and does not synchronize the host.
+ * - Return value 0 = success, negative = error (see GS_ERR_*).  Argument
+ *   validation happens before any device work, so invalid input never
+ *   launches a kernel.  No C++ exception crosses this interface.
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_VERSION 100
+
+/* status codes */
+#define GS_OK               0
+#define GS_NOT_CONVERGED    1   /* gs_solve hit max_iter; x holds the last iterate */
+#define GS_ERR_INVALID_ARG (-1) /* NULL pointer, bad dim/J/M/flags/options      */
+#define GS_ERR_UNSUPPORTED (-2) /* p outside 1..8, 2^J < 2p, grid too large      */
+#define GS_ERR_BAD_NODES   (-3) /* non-finite frequency, negative/non-finite weight */
+#define GS_ERR_NOMEM       (-4) /* device or host allocation failed              */
+#define GS_ERR_HIP         (-5) /* HIP runtime error (text via gs_strerror)       */
+#define GS_ERR_BREAKDOWN   (-6) /* CGLS breakdown: ||A p||^2 <= 0 or non-finite  */
+#define GS_ERR_PRECISION   (-7) /* requested precision not held by this plan     */
+
+/* plan precision */
+#define GS_F64        0  /* applies in FP64, complex128 vectors                       */
+#define GS_F32        1  /* applies in FP32, complex64 vectors                        */
+#define GS_F32_MIXED  2  /* FP32 applies plus FP64 data for refinement (both held)    */
+
+/* apply flags */
+#define GS_WEIGHTED  1   /* apply W^{1/2} T (resp. T^H W^{1/2}) instead of T (T^H)      */
+#define GS_SORTED    2   /* sample vectors are in the plan's internal point order       */
+#define GS_APPLY_F64 4   /* on a GS_F32_MIXED plan: run the FP64 apply (complex128 IO)  */
+
+typedef struct gs_plan gs_plan_t;
+
+/*
+ * gs_plan -- build the matrix-free representation of T (the paper's
+ * Freq2Wave, Sec. 6.2; its "init").
+ *   out        receives the handle (freed with gs_destroy).
+ *   dim        1 or 2.
+ *   J          scale, N = 2^J coefficients per dimension; 1 <= J <= 13, 2^J >= 2p.
+ *   p          vanishing moments: 1 = Haar, 2..8 = Daubechies dbp with CDV
+ *              boundary functions (App. A.1).
+ *   M          number of samples, >= 1.
+ *   xi         HOST array of M*dim doubles (interleaved for dim 2), finite.
+ *   mu         HOST array of M non-negative finite weights (Voronoi measures,
+ *              App. B), or NULL for unit weights.
+ *   precision  GS_F64, GS_F32 or GS_F32_MIXED.
+ *   stream     stream for the uploads.
+ * Host inputs are copied; the caller may free them on return.  The plan owns
+ * all of its device memory (point data, transform grids, solver vectors).
+ * A plan is not thread-safe: calls on one plan share its workspace and must
+ * be ordered on one stream.
+ */
+int gs_plan(gs_plan_t** out, int dim, int J, int p, int64_t M, const double* xi,
+            const double* mu, int precision, void* stream);
+
+/*
+ * gs_apply_T -- y = T x (or W^{1/2} T x with GS_WEIGHTED).
+ * Sec. 4: T x = L x_L + D NFFT(x_I) + R x_R; Sec. 5 / App. C: nine blocks,
+ * interior by a 2D NFFT, sides by 1D NFFTs, corners dense.
+ *   x  device, N^dim complex (row-major X[i][j] in 2D).
+ *   y  device, M complex; in the caller's point order unless GS_SORTED.
+ * Element type: complex128 for GS_F64 plans and GS_APPLY_F64, else complex64.
+ */
+int gs_apply_T(const gs_plan_t* plan, const void* x, void* y, int flags, void* stream);
+
+/*
+ * gs_apply_TH -- x = T^H u (or T^H W^{1/2} u with GS_WEIGHTED); App. C
+ * adjoint, same layouts and element types as gs_apply_T.  Deterministic:
+ * repeated calls give bitwise-identical results (no atomics).
+ */
+int gs_apply_TH(const gs_plan_t* plan, const void* u, void* x, int flags, void* stream);
+
+/* CGLS options / results (Sec. 2: conjugate gradients on the LS problem). */
+typedef struct gs_solve_opts {
+    double rel_tol;        /* stop when ||A^H(b - A x)|| <= rel_tol ||A^H b||, A = W^{1/2}T */
+    int    max_iter;       /* >= 1                                                        */
+    int    warm_start;     /* nonzero: x holds x0 on entry; else x0 = 0                  */
+    int    refine_fp64;    /* GS_F32_MIXED plans: FP64 residual refinement at the end    */
+    int    max_restarts;   /* refinement restarts allowed (mixed form), >= 0             */
+    int    check_every;    /* iterations between host reads of the stop flag (>= 1)      */
+    double* history;       /* optional HOST buffer for the residual history, or NULL     */
+    int    history_len;    /* its length                                                 */
+} gs_solve_opts;
+
+typedef struct gs_solve_info {
+    int    iterations;          /* CGLS iterations run (all restarts)                  */
+    int    restarts;            /* refinement restarts taken                            */
+    int    status;              /* GS_OK, GS_NOT_CONVERGED or GS_ERR_BREAKDOWN          */
+    double rel_residual;        /* final relative normal residual (recurred)           */
+    double rel_residual_fp64;   /* recomputed with FP64 applies (mixed form), else -1  */
+} gs_solve_info;
+
+/*
+ * gs_solve -- weighted LS solution argmin ||W^{1/2}(T x - y)|| by CGLS
+ * (Sec. 2, Sec. 4.1).  y: device, M complex128 in caller order; x: device,
+ * N^dim complex128 (read as x0 when opts->warm_start).  All CGLS vectors and
+ * reductions are FP64 and device-resident; applies run in the plan's
+ * precision.  Returns GS_OK, GS_NOT_CONVERGED (x = last iterate) or an error.
+ * Synchronizes `stream` every opts->check_every iterations.
+ */
+int gs_solve(const gs_plan_t* plan, const void* y, void* x, const gs_solve_opts* opts,
+             gs_solve_info* info, void* stream);
+
+/* Releases every resource of the plan (NULL is ignored). */
+void gs_destroy(gs_plan_t* plan);
+
+/* Plan geometry, for callers that size buffers. */
+typedef struct gs_plan_info {
+    int     dim, J, p, N, precision;
+    int64_t M;
+    int     grid_n;          /* oversampled NFFT grid size per dimension (2N) */
+    int     window_w32;      /* KB window taps per dimension, FP32 path (0 if absent) */
+    int     window_w64;      /* KB window taps per dimension, FP64 path (0 if absent) */
+    int64_t device_bytes;    /* device memory held by the plan */
+} gs_plan_info;
+int gs_get_plan_info(const gs_plan_t* plan, gs_plan_info* info);
+
+/* Copies the plan's point permutation (internal order -> caller index) to a
+ * HOST buffer of M int32. */
+int gs_get_permutation(const gs_plan_t* plan, int32_t* perm_host);
+
+const char* gs_strerror(int code);
+int gs_version(void);
+
+/* ------------------------------------------------------------------------
+ * Host-only basis queries (no device work; usable without a GPU).
+ * ------------------------------------------------------------------------ */
+
+/* Daubechies taps h_k, k = -p+1..p (App. A, m0(0) = 1), into h[2p]. */
+int gs_filter_taps(int p, double* h);
+
+/*
+ * Boundary recursion data of App. A.1 for p >= 2: U (p x p, row-major),
+ * V (p x (2p-1), row-major, columns m = p..3p-2) and v1(0) (p), for the left
+ * edge and for the right edge.  Any output pointer may be NULL.
+ */
+int gs_boundary_filters(int p, double* U_left, double* V_left, double* v0_left,
+                        double* U_right, double* V_right, double* v0_right);
+
+/*
+ * 1D basis values at host points, FP64: out[m*(2nb+1) + c] (complex128,
+ * interleaved) with nb = 0 for Haar else p and channel c:
+ *   c <  nb      : column c        (left boundary)    2^{-J/2} e^{+i pi xi} phiL_c(2^-J xi)
+ *   c == nb      : the interior scale D = 2^{-J/2} phi-hat(2^-J xi)
+ *   c >  nb      : column N-1-(c-nb-1) (right boundary) 2^{-J/2} e^{-i pi xi} phiR_{c-nb-1}(2^-J xi)
+ * (Sec. 4 entries of T; an interior column n is D * exp(-2 pi i (n-N/2) 2^-J xi).)
+ */
+int gs_eval_basis_1d(int J, int p, int64_t M, const double* xi, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GS_H */

@@ -26,6 +26,24 @@ from . import cdv
 from . import daubechies as db
 
 
+def unit_phase(k, eta, sign: float = -1.0) -> np.ndarray:
+    """exp(sign 2 pi i k eta) as an outer product over integer k and real eta.
+    The argument k*eta is reduced modulo 1 in x87 extended precision before the
+    exponential: in plain FP64 the product k*eta ~ N/2 carries an absolute
+    rounding error ~ 1e-11 at N = 16384."""
+    kk = np.asarray(k, dtype=np.longdouble)
+    ee = np.asarray(eta, dtype=np.float64).astype(np.longdouble)
+    t = np.multiply.outer(kk, ee)
+    frac = (t - np.round(t)).astype(np.float64)
+    return np.exp(sign * 2j * np.pi * frac)
+
+
+def half_turn_phase(xi, sign: float) -> np.ndarray:
+    """exp(sign i pi xi) with the exact reduction xi mod 2."""
+    r = np.fmod(np.asarray(xi, dtype=np.float64), 2.0)
+    return np.exp(sign * 1j * np.pi * r)
+
+
 def n_boundary(p: int) -> int:
     return 0 if p == 1 else p
 
@@ -46,13 +64,13 @@ def columns_1d(xi, J: int, p: int) -> np.ndarray:
     ph = db.phi_hat(eta, p)
     nb = n_boundary(p)
     k = np.arange(nb, N - nb) - N // 2
-    B[nb:N - nb] = scale * np.exp(-2j * np.pi * np.multiply.outer(k, eta)) * ph[None, :]
+    B[nb:N - nb] = scale * unit_phase(k, eta, -1.0) * ph[None, :]
     if nb:
         L = cdv.left_phi_hat(eta, p)                 # (p, M)
         R = cdv.right_phi_hat(eta, p)
-        B[:nb] = scale * np.exp(1j * np.pi * xi)[None, :] * L
+        B[:nb] = scale * half_turn_phase(xi, +1.0)[None, :] * L
         # column N-1-k holds phi^R_k
-        B[N - nb:] = (scale * np.exp(-1j * np.pi * xi)[None, :] * R)[::-1]
+        B[N - nb:] = (scale * half_turn_phase(xi, -1.0)[None, :] * R)[::-1]
     return B
 
 

@@ -10,15 +10,21 @@ import mpmath
 import numpy as np
 
 
+def _phase(xi, k, sign):
+    """exp(sign 2 pi i xi k), argument reduced mod 1 in extended precision."""
+    t = np.multiply.outer(np.asarray(xi, np.float64).astype(np.longdouble), np.asarray(k, np.longdouble))
+    return np.exp(sign * 2j * np.pi * (t - np.round(t)).astype(np.float64))
+
+
 def ndft_1d(x, xi):
     N = len(x)
     k = np.arange(-N // 2, N // 2)
-    return np.exp(-2j * np.pi * np.multiply.outer(np.asarray(xi, float), k)) @ np.asarray(x, complex)
+    return _phase(xi, k, -1.0) @ np.asarray(x, complex)
 
 
 def ndft_adjoint_1d(y, xi, N):
     k = np.arange(-N // 2, N // 2)
-    return np.exp(2j * np.pi * np.multiply.outer(k, np.asarray(xi, float))) @ np.asarray(y, complex)
+    return _phase(xi, k, +1.0).T @ np.asarray(y, complex)
 
 
 def ndft_2d(X, xi2):
@@ -27,8 +33,8 @@ def ndft_2d(X, xi2):
     k1 = np.arange(-N1 // 2, N1 // 2)
     k2 = np.arange(-N2 // 2, N2 // 2)
     xi2 = np.asarray(xi2, float)
-    E1 = np.exp(-2j * np.pi * np.multiply.outer(xi2[:, 0], k1))     # (M, N1)
-    E2 = np.exp(-2j * np.pi * np.multiply.outer(xi2[:, 1], k2))     # (M, N2)
+    E1 = _phase(xi2[:, 0], k1, -1.0)     # (M, N1)
+    E2 = _phase(xi2[:, 1], k2, -1.0)     # (M, N2)
     return np.einsum("mi,ij,mj->m", E1, np.asarray(X, complex), E2)
 
 
@@ -36,8 +42,8 @@ def ndft_adjoint_2d(y, xi2, N1, N2):
     k1 = np.arange(-N1 // 2, N1 // 2)
     k2 = np.arange(-N2 // 2, N2 // 2)
     xi2 = np.asarray(xi2, float)
-    E1 = np.exp(2j * np.pi * np.multiply.outer(k1, xi2[:, 0]))      # (N1, M)
-    E2 = np.exp(2j * np.pi * np.multiply.outer(xi2[:, 1], k2))      # (M, N2)
+    E1 = _phase(xi2[:, 0], k1, +1.0).T   # (N1, M)
+    E2 = _phase(xi2[:, 1], k2, +1.0)     # (M, N2)
     return E1 @ (np.asarray(y, complex)[:, None] * E2)
 
 

@@ -1,0 +1,391 @@
+// C ABI entry points of libgs: plan construction ("init" of the paper's
+// Freq2Wave, Sec. 6.2), applies of T and T^H, plan queries and the host-only
+// basis queries.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <stdexcept>
+#include <thread>
+#include <vector>
+
+#include "common.hpp"
+#include "host_math.hpp"
+
+namespace gs {
+size_t adjoint_part_elems(int dim, int64_t M, int nb, int ng);
+}
+
+namespace {
+
+thread_local char g_hip_msg[256] = "";
+
+int hip_fail(hipError_t e) {
+    std::snprintf(g_hip_msg, sizeof g_hip_msg, "HIP error %d: %s", (int)e, hipGetErrorString(e));
+    return GS_ERR_HIP;
+}
+
+template <class P>
+hipError_t dalloc(gs::Plan& pl, P*& ptr, size_t elems) {
+    ptr = nullptr;
+    if (elems == 0) return hipSuccess;
+    void* v = nullptr;
+    hipError_t e = hipMalloc(&v, elems * sizeof(P));
+    if (e != hipSuccess) return e;
+    ptr = static_cast<P*>(v);
+    pl.bytes += (int64_t)(elems * sizeof(P));
+    return hipSuccess;
+}
+
+template <class P>
+void dfree(P*& ptr) {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+}
+
+template <class T>
+void free_prec(gs::PrecData<T>& d) {
+    dfree(d.pos); dfree(d.chx); dfree(d.chy); dfree(d.smu); dfree(d.win); dfree(d.deap); dfree(d.tw);
+    dfree(d.grid); dfree(d.sr); dfree(d.sc); dfree(d.part); dfree(d.vbuf); dfree(d.ybuf); dfree(d.xbuf);
+    d.present = false;
+}
+
+void free_plan(gs::Plan& P) {
+    free_prec(P.d64);
+    free_prec(P.d32);
+    dfree(P.perm); dfree(P.cell_start);
+    dfree(P.smu64); dfree(P.b); dfree(P.r); dfree(P.q); dfree(P.ps); dfree(P.ss);
+    dfree(P.q32); dfree(P.r32); dfree(P.p32); dfree(P.s32);
+    dfree(P.red); dfree(P.scal); dfree(P.hist);
+    if (P.host_scal) (void)hipHostFree(P.host_scal);
+    P.host_scal = nullptr;
+}
+
+struct HostPoints {
+    std::vector<uint64_t> pos;             // [dim][M]
+    std::vector<gs::cd> ch;                // [dim][M][nch]
+    std::vector<int32_t> perm;             // internal -> caller
+    std::vector<int32_t> cell_start;       // ncells + 1
+};
+
+int hw_threads() {
+    unsigned n = std::thread::hardware_concurrency();
+    return n == 0 ? 4 : (int)std::min(n, 64u);
+}
+
+uint64_t fixed_point_frac(double xi, int J) {
+    const double eta = std::ldexp(xi, -J);
+    const double f = eta - std::floor(eta);   // exact, in [0, 1)
+    long double r = std::nearbyint(std::ldexp((long double)f, 64));
+    if (r >= std::ldexp((long double)1, 64)) r = 0;   // wraps to 0 on the torus
+    return (uint64_t)r;
+}
+
+template <class T>
+hipError_t upload_prec(gs::Plan& P, const HostPoints& H, const std::vector<double>& smu_sorted, int w, int deg,
+                       double beta, hipStream_t s) {
+    using namespace gs;
+    PrecData<T>& d = prec<T>(P);
+    const size_t M = P.M, nch = 2 * P.nb + 1;
+    d.present = true;
+    d.w = w;
+    d.deg = deg;
+    // positions
+    GS_HIP_TRY(dalloc(P, d.pos, (size_t)P.dim * M));
+    {
+        std::vector<P_t<T>> hp((size_t)P.dim * M);
+        for (size_t i = 0; i < hp.size(); ++i) hp[i] = (P_t<T>)(H.pos[i] >> (64 - posw<T>::bits));
+        GS_HIP_TRY(hipMemcpy(d.pos, hp.data(), hp.size() * sizeof(P_t<T>), hipMemcpyHostToDevice));
+    }
+    // channels (SoA: [nch][M] per dimension), internal order
+    for (int dm = 0; dm < P.dim; ++dm) {
+        cx<T>*& dst = dm == 0 ? d.chx : d.chy;
+        GS_HIP_TRY(dalloc(P, dst, nch * M));
+        std::vector<cx<T>> hc(nch * M);
+        for (size_t q = 0; q < M; ++q) {
+            const cd* src = &H.ch[((size_t)dm * M + q) * nch];
+            for (size_t c = 0; c < nch; ++c) hc[c * M + q] = mk<T>((T)src[c].real(), (T)src[c].imag());
+        }
+        GS_HIP_TRY(hipMemcpy(dst, hc.data(), hc.size() * sizeof(cx<T>), hipMemcpyHostToDevice));
+    }
+    {
+        GS_HIP_TRY(dalloc(P, d.smu, M));
+        std::vector<T> hs(M);
+        for (size_t q = 0; q < M; ++q) hs[q] = (T)smu_sorted[q];
+        GS_HIP_TRY(hipMemcpy(d.smu, hs.data(), M * sizeof(T), hipMemcpyHostToDevice));
+    }
+    // window and deapodization
+    const KBWindow kb = make_window(w, deg, beta);
+    {
+        GS_HIP_TRY(dalloc(P, d.win, kb.coef.size()));
+        std::vector<T> hw(kb.coef.begin(), kb.coef.end());
+        GS_HIP_TRY(hipMemcpy(d.win, hw.data(), hw.size() * sizeof(T), hipMemcpyHostToDevice));
+    }
+    {
+        GS_HIP_TRY(dalloc(P, d.deap, (size_t)P.N));
+        std::vector<T> hd(P.N);
+        for (int j = 0; j < P.N; ++j) {
+            const bool interior = j >= P.nb && j < P.N - P.nb;
+            hd[j] = interior ? (T)(1.0 / kb.ft((double)(j - P.N / 2) / P.ng)) : T(0);
+        }
+        GS_HIP_TRY(hipMemcpy(d.deap, hd.data(), hd.size() * sizeof(T), hipMemcpyHostToDevice));
+    }
+    {
+        GS_HIP_TRY(dalloc(P, d.tw, (size_t)P.ng));
+        std::vector<cx<T>> ht(P.ng);
+        for (int k = 0; k < P.ng; ++k) {
+            const long double a = -2.0L * 3.14159265358979323846264338327950288L * k / P.ng;
+            ht[k] = mk<T>((T)std::cos(a), (T)std::sin(a));
+        }
+        GS_HIP_TRY(hipMemcpy(d.tw, ht.data(), ht.size() * sizeof(cx<T>), hipMemcpyHostToDevice));
+    }
+    // workspace
+    const size_t gsz = P.dim == 2 ? (size_t)P.ng * P.ng : (size_t)P.ng;
+    GS_HIP_TRY(dalloc(P, d.grid, gsz));
+    if (P.dim == 2 && P.nb) {
+        GS_HIP_TRY(dalloc(P, d.sr, (size_t)2 * P.nb * P.ng));
+        GS_HIP_TRY(dalloc(P, d.sc, (size_t)2 * P.nb * P.ng));
+    }
+    d.part_elems = adjoint_part_elems(P.dim, P.M, P.nb, P.ng);
+    GS_HIP_TRY(dalloc(P, d.part, d.part_elems));
+    GS_HIP_TRY(dalloc(P, d.vbuf, M));
+    GS_HIP_TRY(dalloc(P, d.ybuf, M));
+    const size_t ncoef = P.dim == 2 ? (size_t)P.N * P.N : (size_t)P.N;
+    GS_HIP_TRY(dalloc(P, d.xbuf, ncoef));
+    (void)s;
+    return hipSuccess;
+}
+
+}  // namespace
+
+namespace gs {
+hipError_t solver_alloc(Plan& P);
+}
+
+extern "C" {
+
+int gs_version(void) { return GS_VERSION; }
+
+const char* gs_strerror(int code) {
+    switch (code) {
+        case GS_OK: return "success";
+        case GS_NOT_CONVERGED: return "CGLS reached max_iter before the tolerance";
+        case GS_ERR_INVALID_ARG: return "invalid argument";
+        case GS_ERR_UNSUPPORTED: return "unsupported configuration (p, J or grid size)";
+        case GS_ERR_BAD_NODES: return "non-finite frequency or negative/non-finite weight";
+        case GS_ERR_NOMEM: return "out of memory";
+        case GS_ERR_HIP: return g_hip_msg[0] ? g_hip_msg : "HIP runtime error";
+        case GS_ERR_BREAKDOWN: return "CGLS breakdown (||A p||^2 <= 0 or non-finite)";
+        case GS_ERR_PRECISION: return "requested precision is not held by this plan";
+        default: return "unknown status";
+    }
+}
+
+int gs_plan(gs_plan_t** out, int dim, int J, int p, int64_t M, const double* xi, const double* mu, int precision,
+            void* stream) {
+    if (!out) return GS_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (dim != 1 && dim != 2) return GS_ERR_INVALID_ARG;
+    if (!xi || M <= 0 || M > (int64_t)std::numeric_limits<int32_t>::max() / 2) return GS_ERR_INVALID_ARG;
+    if (precision != GS_F64 && precision != GS_F32 && precision != GS_F32_MIXED) return GS_ERR_INVALID_ARG;
+    if (p < 1 || p > 8) return GS_ERR_UNSUPPORTED;
+    if (J < 1 || J > (dim == 2 ? 11 : 20)) return GS_ERR_UNSUPPORTED;
+    if ((1 << J) < 2 * p) return GS_ERR_UNSUPPORTED;
+    for (int64_t i = 0; i < M * dim; ++i)
+        if (!std::isfinite(xi[i])) return GS_ERR_BAD_NODES;
+    if (mu)
+        for (int64_t i = 0; i < M; ++i)
+            if (!std::isfinite(mu[i]) || mu[i] < 0) return GS_ERR_BAD_NODES;
+
+    std::unique_ptr<gs_plan_t> h;
+    try {
+        h.reset(new gs_plan_t());
+    } catch (...) {
+        return GS_ERR_NOMEM;
+    }
+    gs::Plan& P = h->impl;
+    P.dim = dim; P.J = J; P.p = p; P.nb = (p == 1) ? 0 : p; P.N = 1 << J; P.M = M; P.precision = precision;
+    P.ng = 2 * P.N; P.G = J + 1;
+    if (dim == 1 && P.ng > gs::FFT_MAX_LDS) {
+        P.lg1 = P.G / 2; P.lg2 = P.G - P.lg1;
+    } else {
+        P.lg1 = P.G; P.lg2 = 0;
+    }
+    P.n1 = 1 << P.lg1; P.n2 = 1 << P.lg2;
+    hipStream_t s = (hipStream_t)stream;
+
+    // ---- host math (FP64 / extended)
+    const int nch = 2 * P.nb + 1;
+    HostPoints H;
+    std::vector<gs::cd> ch;
+    try {
+        (void)gs::basis_data(p);
+        std::vector<gs::cd> tmp((size_t)M * nch);
+        ch.resize((size_t)dim * M * nch);
+        for (int dm = 0; dm < dim; ++dm) {
+            gs::eval_basis_1d(J, p, M, xi + dm, dim, tmp.data(), hw_threads());
+            std::copy(tmp.begin(), tmp.end(), ch.begin() + (size_t)dm * M * nch);
+        }
+    } catch (const std::bad_alloc&) {
+        return GS_ERR_NOMEM;
+    } catch (...) {
+        return GS_ERR_UNSUPPORTED;
+    }
+    // positions and cell keys
+    std::vector<uint64_t> pos((size_t)dim * M);
+    std::vector<int32_t> key(M);
+    for (int64_t m = 0; m < M; ++m) {
+        int64_t k = 0;
+        for (int dm = 0; dm < dim; ++dm) {
+            const uint64_t u = fixed_point_frac(xi[m * dim + dm], J);
+            pos[(size_t)dm * M + m] = u;
+            k = (k << P.G) | (int64_t)(u >> (64 - P.G));
+        }
+        key[m] = (int32_t)k;
+    }
+    // counting sort by cell (stable)
+    const int64_t ncells = dim == 2 ? (int64_t)P.ng * P.ng : P.ng;
+    H.cell_start.assign(ncells + 1, 0);
+    for (int64_t m = 0; m < M; ++m) H.cell_start[key[m] + 1]++;
+    for (int64_t c = 0; c < ncells; ++c) H.cell_start[c + 1] += H.cell_start[c];
+    H.perm.resize(M);
+    {
+        std::vector<int32_t> fill(H.cell_start.begin(), H.cell_start.end() - 1);
+        for (int64_t m = 0; m < M; ++m) H.perm[fill[key[m]]++] = (int32_t)m;
+    }
+    H.pos.resize((size_t)dim * M);
+    H.ch.resize((size_t)dim * M * nch);
+    std::vector<double> smu(M);
+    for (int64_t q = 0; q < M; ++q) {
+        const int64_t m = H.perm[q];
+        for (int dm = 0; dm < dim; ++dm) {
+            H.pos[(size_t)dm * M + q] = pos[(size_t)dm * M + m];
+            std::copy_n(&ch[((size_t)dm * M + m) * nch], nch, &H.ch[((size_t)dm * M + q) * nch]);
+        }
+        smu[q] = mu ? std::sqrt(mu[m]) : 1.0;
+    }
+
+    // ---- device
+    hipError_t e = hipSuccess;
+    do {
+        if ((e = dalloc(P, P.perm, (size_t)M)) != hipSuccess) break;
+        if ((e = hipMemcpy(P.perm, H.perm.data(), M * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess) break;
+        if ((e = dalloc(P, P.cell_start, (size_t)ncells + 1)) != hipSuccess) break;
+        if ((e = hipMemcpy(P.cell_start, H.cell_start.data(), (ncells + 1) * sizeof(int32_t),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            break;
+        if (precision == GS_F64 || precision == GS_F32_MIXED)
+            if ((e = upload_prec<double>(P, H, smu, gs::W64, gs::DEG64, 2.35 * gs::W64, s)) != hipSuccess) break;
+        if (precision == GS_F32 || precision == GS_F32_MIXED)
+            if ((e = upload_prec<float>(P, H, smu, gs::W32, gs::DEG32, 2.35 * gs::W32, s)) != hipSuccess) break;
+        if ((e = gs::solver_alloc(P)) != hipSuccess) break;
+        if ((e = hipMemcpy(P.smu64, smu.data(), M * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) break;
+    } while (0);
+    if (e != hipSuccess) {
+        free_plan(P);
+        return e == hipErrorOutOfMemory ? GS_ERR_NOMEM : hip_fail(e);
+    }
+    *out = h.release();
+    return GS_OK;
+}
+
+void gs_destroy(gs_plan_t* plan) {
+    if (!plan) return;
+    free_plan(plan->impl);
+    delete plan;
+}
+
+static int pick_apply(const gs_plan_t* plan, const void* a, const void* b, int flags, bool& use64) {
+    if (!plan || !a || !b) return GS_ERR_INVALID_ARG;
+    if (flags & ~(GS_WEIGHTED | GS_SORTED | GS_APPLY_F64)) return GS_ERR_INVALID_ARG;
+    const gs::Plan& P = plan->impl;
+    if (P.precision == GS_F64) use64 = true;
+    else if (P.precision == GS_F32) {
+        if (flags & GS_APPLY_F64) return GS_ERR_PRECISION;
+        use64 = false;
+    } else use64 = (flags & GS_APPLY_F64) != 0;
+    return GS_OK;
+}
+
+int gs_apply_T(const gs_plan_t* plan, const void* x, void* y, int flags, void* stream) {
+    bool use64 = false;
+    int rc = pick_apply(plan, x, y, flags, use64);
+    if (rc) return rc;
+    hipError_t e = use64 ? gs::launch_apply_T<double>(plan->impl, (const gs::cx<double>*)x, (gs::cx<double>*)y, flags,
+                                                      (hipStream_t)stream)
+                         : gs::launch_apply_T<float>(plan->impl, (const gs::cx<float>*)x, (gs::cx<float>*)y, flags,
+                                                     (hipStream_t)stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e);
+}
+
+int gs_apply_TH(const gs_plan_t* plan, const void* u, void* x, int flags, void* stream) {
+    bool use64 = false;
+    int rc = pick_apply(plan, u, x, flags, use64);
+    if (rc) return rc;
+    hipError_t e = use64 ? gs::launch_apply_TH<double>(plan->impl, (const gs::cx<double>*)u, (gs::cx<double>*)x,
+                                                       flags, (hipStream_t)stream)
+                         : gs::launch_apply_TH<float>(plan->impl, (const gs::cx<float>*)u, (gs::cx<float>*)x, flags,
+                                                      (hipStream_t)stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e);
+}
+
+int gs_get_plan_info(const gs_plan_t* plan, gs_plan_info* info) {
+    if (!plan || !info) return GS_ERR_INVALID_ARG;
+    const gs::Plan& P = plan->impl;
+    info->dim = P.dim; info->J = P.J; info->p = P.p; info->N = P.N; info->precision = P.precision;
+    info->M = P.M; info->grid_n = P.ng;
+    info->window_w32 = P.d32.present ? P.d32.w : 0;
+    info->window_w64 = P.d64.present ? P.d64.w : 0;
+    info->device_bytes = P.bytes;
+    return GS_OK;
+}
+
+int gs_get_permutation(const gs_plan_t* plan, int32_t* perm_host) {
+    if (!plan || !perm_host) return GS_ERR_INVALID_ARG;
+    hipError_t e = hipMemcpy(perm_host, plan->impl.perm, plan->impl.M * sizeof(int32_t), hipMemcpyDeviceToHost);
+    return e == hipSuccess ? GS_OK : hip_fail(e);
+}
+
+int gs_filter_taps(int p, double* h) {
+    if (!h) return GS_ERR_INVALID_ARG;
+    try {
+        const gs::BasisData& b = gs::basis_data(p);
+        std::copy(b.taps.begin(), b.taps.end(), h);
+    } catch (...) {
+        return GS_ERR_UNSUPPORTED;
+    }
+    return GS_OK;
+}
+
+int gs_boundary_filters(int p, double* U_left, double* V_left, double* v0_left, double* U_right, double* V_right,
+                        double* v0_right) {
+    if (p < 2) return GS_ERR_UNSUPPORTED;
+    try {
+        const gs::BasisData& b = gs::basis_data(p);
+        if (U_left) std::copy(b.left.U.begin(), b.left.U.end(), U_left);
+        if (V_left) std::copy(b.left.V.begin(), b.left.V.end(), V_left);
+        if (v0_left) std::copy(b.left.v0.begin(), b.left.v0.end(), v0_left);
+        if (U_right) std::copy(b.right.U.begin(), b.right.U.end(), U_right);
+        if (V_right) std::copy(b.right.V.begin(), b.right.V.end(), V_right);
+        if (v0_right) std::copy(b.right.v0.begin(), b.right.v0.end(), v0_right);
+    } catch (...) {
+        return GS_ERR_UNSUPPORTED;
+    }
+    return GS_OK;
+}
+
+int gs_eval_basis_1d(int J, int p, int64_t M, const double* xi, double* out) {
+    if (!xi || !out || M < 0) return GS_ERR_INVALID_ARG;
+    if (p < 1 || p > 8 || J < 1 || J > 30 || (1LL << J) < 2 * p) return GS_ERR_UNSUPPORTED;
+    for (int64_t i = 0; i < M; ++i)
+        if (!std::isfinite(xi[i])) return GS_ERR_BAD_NODES;
+    try {
+        gs::eval_basis_1d(J, p, M, xi, 1, reinterpret_cast<gs::cd*>(out), hw_threads());
+    } catch (...) {
+        return GS_ERR_UNSUPPORTED;
+    }
+    return GS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,444 @@
+// Device-resident CGLS for the weighted least-squares problem
+// argmin ||W^{1/2}(T x - y)|| (Sec. 2 eq. least_squares; Sec. 4.1 eq.
+// weighted_least_squares; the paper's "conjugate gradient procedure").
+//
+// A = W^{1/2} T, b = W^{1/2} y.  Iteration (CG on the normal equations):
+//   q = A p; delta = ||q||^2; alpha = gamma/delta; x += alpha p; r -= alpha q;
+//   s = A^H r; gamma' = ||s||^2; p = s + (gamma'/gamma) p; gamma = gamma'.
+// Stop when sqrt(gamma) <= tol * ||A^H b||.  All vectors, reductions and
+// scalars are FP64 and stay on the device; the applies run in the plan's
+// precision.  Reductions are two-stage with a fixed block count and a fixed
+// summation order, so results are bitwise reproducible.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+
+namespace gs {
+
+constexpr int RB = 512;      // reduction blocks (fixed -> deterministic)
+constexpr int RT = 256;      // threads per reduction block
+
+enum Scal { S_GAMMA = 0, S_DELTA, S_ALPHA, S_REF, S_TOL2, S_DONE, S_BREAK, S_ITER, S_REF64, S_NSCAL = 16 };
+
+template <class T> __device__ inline cx<double> to64(cx<T> v) { return mk<double>((double)v.x, (double)v.y); }
+
+__device__ inline double block_sum(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = RT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// sum of the RB partials, same order in every block
+__device__ inline double sum_partials(const double* __restrict__ red, double* sh) {
+    double v = 0;
+    for (int i = threadIdx.x; i < RB; i += RT) v += red[i];
+    return block_sum(v, sh);
+}
+
+template <class T>
+__global__ void __launch_bounds__(RT) norm2_partial_kernel(const cx<T>* __restrict__ v, int64_t n, double* __restrict__ red) {
+    __shared__ double sh[RT];
+    double acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)RB * RT) {
+        const cx<double> a = to64(v[i]);
+        acc += a.x * a.x + a.y * a.y;
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) red[blockIdx.x] = s;
+}
+
+// b = sqrt(mu) * y[perm]; r = b (x0 = 0) ; optional FP32 copy of r
+template <class Tr>
+__global__ void init_b_kernel(const cx<double>* __restrict__ y, const int32_t* __restrict__ perm,
+                              const double* __restrict__ smu, int64_t M, cx<double>* __restrict__ b,
+                              cx<double>* __restrict__ r, cx<Tr>* __restrict__ rT) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const cx<double> v = cscale(y[perm[m]], smu[m]);
+    b[m] = v;
+    r[m] = v;
+    if (rT) rT[m] = mk<Tr>((Tr)v.x, (Tr)v.y);
+}
+
+// r = b - q  (q = A x in apply precision), optional FP32 copy
+template <class T, class Tr>
+__global__ void residual_kernel(const cx<double>* __restrict__ b, const cx<T>* __restrict__ q, int64_t M,
+                                cx<double>* __restrict__ r, cx<Tr>* __restrict__ rT) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const cx<double> v = csub(b[m], to64(q[m]));
+    r[m] = v;
+    if (rT) rT[m] = mk<Tr>((Tr)v.x, (Tr)v.y);
+}
+
+template <class T>
+__global__ void convert_kernel(const cx<double>* __restrict__ a, cx<T>* __restrict__ o, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = mk<T>((T)a[i].x, (T)a[i].y);
+}
+
+template <class T>
+__global__ void zero_kernel(cx<T>* __restrict__ o, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = czero<T>();
+}
+
+// p = s (in FP64 and, if FP32 applies, FP32); gamma = ||s||^2 is reduced separately
+template <class T, class Tp>
+__global__ void init_p_kernel(const cx<T>* __restrict__ s, cx<double>* __restrict__ p, cx<Tp>* __restrict__ pT,
+                              int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const cx<double> v = to64(s[i]);
+    p[i] = v;
+    if (pT) pT[i] = mk<Tp>((Tp)v.x, (Tp)v.y);
+}
+
+// scalar setup after the first A^H r: gamma, ref, done flag
+__global__ void start_scalars_kernel(double* __restrict__ scal, const double* __restrict__ red, int set_ref,
+                                     double* __restrict__ hist, int hist_len) {
+    __shared__ double sh[RT];
+    const double g = sum_partials(red, sh);
+    if (threadIdx.x == 0) {
+        scal[S_GAMMA] = g;
+        if (set_ref) scal[S_REF] = sqrt(g);
+        scal[S_ITER] = 0;
+        scal[S_BREAK] = 0;
+        const double ref = scal[S_REF];
+        scal[S_DONE] = (ref == 0.0 || g <= scal[S_TOL2] * ref * ref) ? 1.0 : 0.0;
+        if (hist && hist_len > 0) hist[0] = ref > 0 ? sqrt(g) / ref : 0.0;
+    }
+}
+
+__global__ void set_ref64_kernel(double* __restrict__ scal, const double* __restrict__ red) {
+    __shared__ double sh[RT];
+    const double g = sum_partials(red, sh);
+    if (threadIdx.x == 0) scal[S_REF64] = sqrt(g);
+}
+
+// x += alpha p ; r -= alpha q ; alpha = gamma / ||q||^2
+template <class T, class Tr>
+__global__ void __launch_bounds__(RT) update_xr_kernel(double* __restrict__ scal, const double* __restrict__ red,
+                                                       cx<double>* __restrict__ x, const cx<double>* __restrict__ p,
+                                                       int64_t nx, cx<double>* __restrict__ r,
+                                                       const cx<T>* __restrict__ q, cx<Tr>* __restrict__ rT,
+                                                       int64_t M) {
+    __shared__ double sh[RT];
+    const double delta = sum_partials(red, sh);
+    if (scal[S_DONE] != 0.0) return;
+    const double alpha = scal[S_GAMMA] / delta;
+    if (!(delta > 0.0) || !isfinite(alpha)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_BREAK] = 1.0;
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        scal[S_DELTA] = delta;
+        scal[S_ALPHA] = alpha;
+    }
+    const int64_t total = nx + M;
+    for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < total; i += (int64_t)gridDim.x * RT) {
+        if (i < nx) {
+            const cx<double> pv = p[i];
+            cx<double> xv = x[i];
+            xv.x += alpha * pv.x;
+            xv.y += alpha * pv.y;
+            x[i] = xv;
+        } else {
+            const int64_t m = i - nx;
+            const cx<double> qv = to64(q[m]);
+            cx<double> rv = r[m];
+            rv.x -= alpha * qv.x;
+            rv.y -= alpha * qv.y;
+            r[m] = rv;
+            if (rT) rT[m] = mk<Tr>((Tr)rv.x, (Tr)rv.y);
+        }
+    }
+}
+
+// p = s + beta p, beta = ||s||^2 / gamma (gamma not yet updated)
+template <class T, class Tp>
+__global__ void __launch_bounds__(RT) update_p_kernel(const double* __restrict__ scal, const double* __restrict__ red,
+                                                      cx<double>* __restrict__ p, const cx<T>* __restrict__ s,
+                                                      cx<Tp>* __restrict__ pT, int64_t nx) {
+    __shared__ double sh[RT];
+    const double gnew = sum_partials(red, sh);
+    if (scal[S_DONE] != 0.0 || scal[S_BREAK] != 0.0) return;
+    const double beta = gnew / scal[S_GAMMA];
+    for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < nx; i += (int64_t)gridDim.x * RT) {
+        const cx<double> sv = to64(s[i]);
+        cx<double> pv = p[i];
+        pv.x = sv.x + beta * pv.x;
+        pv.y = sv.y + beta * pv.y;
+        p[i] = pv;
+        if (pT) pT[i] = mk<Tp>((Tp)pv.x, (Tp)pv.y);
+    }
+}
+
+// gamma = ||s||^2 ; iteration count, history, convergence test
+__global__ void step_scalars_kernel(double* __restrict__ scal, const double* __restrict__ red,
+                                    double* __restrict__ hist, int hist_len) {
+    __shared__ double sh[RT];
+    const double gnew = sum_partials(red, sh);
+    if (threadIdx.x != 0) return;
+    if (scal[S_DONE] != 0.0) return;
+    if (scal[S_BREAK] != 0.0) {
+        scal[S_DONE] = 1.0;
+        return;
+    }
+    scal[S_GAMMA] = gnew;
+    const double it = scal[S_ITER] + 1.0;
+    scal[S_ITER] = it;
+    const double ref = scal[S_REF];
+    if (hist && (int)it < hist_len) hist[(int)it] = sqrt(gnew) / ref;
+    if (gnew <= scal[S_TOL2] * ref * ref) scal[S_DONE] = 1.0;
+}
+
+__global__ void set_scalar_kernel(double* __restrict__ scal, int idx, double v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) scal[idx] = v;
+}
+
+inline int nb256(int64_t n) { return (int)std::max<int64_t>(1, (n + 255) / 256); }
+
+hipError_t solver_alloc(Plan& P) {
+    auto alloc = [&](auto*& ptr, size_t n) -> hipError_t {
+        void* v = nullptr;
+        hipError_t e = hipMalloc(&v, n * sizeof(*ptr));
+        if (e != hipSuccess) return e;
+        ptr = static_cast<std::remove_reference_t<decltype(ptr)>>(v);
+        P.bytes += (int64_t)(n * sizeof(*ptr));
+        return hipSuccess;
+    };
+    const size_t M = P.M, nx = P.dim == 2 ? (size_t)P.N * P.N : (size_t)P.N;
+    GS_HIP_TRY(alloc(P.smu64, M));
+    GS_HIP_TRY(alloc(P.b, M));
+    GS_HIP_TRY(alloc(P.r, M));
+    GS_HIP_TRY(alloc(P.q, M));
+    GS_HIP_TRY(alloc(P.ps, nx));
+    GS_HIP_TRY(alloc(P.ss, nx));
+    if (P.d32.present) {
+        GS_HIP_TRY(alloc(P.q32, M));
+        GS_HIP_TRY(alloc(P.r32, M));
+        GS_HIP_TRY(alloc(P.p32, nx));
+        GS_HIP_TRY(alloc(P.s32, nx));
+    }
+    P.red_blocks = RB;
+    GS_HIP_TRY(alloc(P.red, (size_t)RB));
+    GS_HIP_TRY(alloc(P.scal, (size_t)S_NSCAL));
+    P.hist_len = 1 << 16;
+    GS_HIP_TRY(alloc(P.hist, (size_t)P.hist_len));
+    void* hs = nullptr;
+    GS_HIP_TRY(hipHostMalloc(&hs, S_NSCAL * sizeof(double), hipHostMallocDefault));
+    P.host_scal = static_cast<double*>(hs);
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------------ solver loop
+
+template <class T>
+struct Ops;
+
+// FP64 applies: operands are the FP64 solver vectors themselves
+template <>
+struct Ops<double> {
+    const Plan& P;
+    cx<double>* qa() const { return P.q; }
+    cx<double>* sa() const { return P.ss; }
+    cx<double>* ra() const { return P.r; }
+    cx<double>* pa() const { return P.ps; }
+    cx<double>* rcopy() const { return nullptr; }
+    cx<double>* pcopy() const { return nullptr; }
+};
+template <>
+struct Ops<float> {
+    const Plan& P;
+    cx<float>* qa() const { return P.q32; }
+    cx<float>* sa() const { return P.s32; }
+    cx<float>* ra() const { return P.r32; }
+    cx<float>* pa() const { return P.p32; }
+    cx<float>* rcopy() const { return P.r32; }
+    cx<float>* pcopy() const { return P.p32; }
+};
+
+constexpr int AFLAGS = GS_WEIGHTED | GS_SORTED;
+
+// Starts CGLS from x (already on device, FP64) given r = b - A x in P.r (and
+// its apply-precision copy).  Computes s = A^H r, gamma, p = s.
+template <class T>
+hipError_t cgls_start(const Plan& P, hipStream_t st, int set_ref, double* hist, int hist_len) {
+    Ops<T> o{P};
+    const int64_t nx = P.dim == 2 ? (int64_t)P.N * P.N : P.N;
+    GS_HIP_TRY(launch_apply_TH<T>(P, o.ra(), o.sa(), AFLAGS, st));
+    hipLaunchKernelGGL((norm2_partial_kernel<T>), dim3(RB), dim3(RT), 0, st, o.sa(), nx, P.red);
+    hipLaunchKernelGGL((init_p_kernel<T, T>), dim3(nb256(nx)), dim3(256), 0, st, o.sa(), P.ps, o.pcopy(), nx);
+    hipLaunchKernelGGL(start_scalars_kernel, dim3(1), dim3(RT), 0, st, P.scal, P.red, set_ref, hist, hist_len);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t cgls_iteration(const Plan& P, cx<double>* x, hipStream_t st, double* hist, int hist_len) {
+    Ops<T> o{P};
+    const int64_t nx = P.dim == 2 ? (int64_t)P.N * P.N : P.N;
+    const int64_t M = P.M;
+    GS_HIP_TRY(launch_apply_T<T>(P, o.pa(), o.qa(), AFLAGS, st));
+    hipLaunchKernelGGL((norm2_partial_kernel<T>), dim3(RB), dim3(RT), 0, st, o.qa(), M, P.red);
+    hipLaunchKernelGGL((update_xr_kernel<T, T>), dim3(1024), dim3(RT), 0, st, P.scal, P.red, x, P.ps, nx, P.r,
+                       o.qa(), o.rcopy(), M);
+    GS_HIP_TRY(hipGetLastError());
+    GS_HIP_TRY(launch_apply_TH<T>(P, o.ra(), o.sa(), AFLAGS, st));
+    hipLaunchKernelGGL((norm2_partial_kernel<T>), dim3(RB), dim3(RT), 0, st, o.sa(), nx, P.red);
+    hipLaunchKernelGGL((update_p_kernel<T, T>), dim3(256), dim3(RT), 0, st, P.scal, P.red, P.ps, o.sa(), o.pcopy(),
+                       nx);
+    hipLaunchKernelGGL(step_scalars_kernel, dim3(1), dim3(RT), 0, st, P.scal, P.red, hist, hist_len);
+    return hipGetLastError();
+}
+
+// r = b - A x with applies of type T (x FP64 on device)
+template <class T>
+hipError_t compute_residual(const Plan& P, const cx<double>* x, hipStream_t st) {
+    Ops<T> o{P};
+    const int64_t nx = P.dim == 2 ? (int64_t)P.N * P.N : P.N;
+    const cx<T>* xin;
+    if constexpr (std::is_same<T, float>::value) {
+        hipLaunchKernelGGL((convert_kernel<float>), dim3(nb256(nx)), dim3(256), 0, st, x, P.p32, nx);
+        xin = P.p32;
+    } else {
+        xin = x;
+    }
+    GS_HIP_TRY(launch_apply_T<T>(P, xin, o.qa(), AFLAGS, st));
+    hipLaunchKernelGGL((residual_kernel<T, T>), dim3(nb256(P.M)), dim3(256), 0, st, P.b, o.qa(), P.M, P.r,
+                       o.rcopy());
+    return hipGetLastError();
+}
+
+// run iterations until done or budget spent; returns iterations used (device count read back)
+template <class T>
+hipError_t cgls_run(const Plan& P, cx<double>* x, hipStream_t st, int budget, int check_every, double* hist,
+                    int hist_len, bool& done, bool& broke) {
+    done = false;
+    broke = false;
+    int it = 0;
+    while (it < budget) {
+        const int n = std::min(check_every, budget - it);
+        for (int k = 0; k < n; ++k) GS_HIP_TRY(cgls_iteration<T>(P, x, st, hist, hist_len));
+        it += n;
+        GS_HIP_TRY(hipMemcpyAsync(P.host_scal, P.scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, st));
+        GS_HIP_TRY(hipStreamSynchronize(st));
+        if (P.host_scal[S_BREAK] != 0.0) {
+            broke = true;
+            return hipSuccess;
+        }
+        if (P.host_scal[S_DONE] != 0.0) {
+            done = true;
+            return hipSuccess;
+        }
+    }
+    return hipSuccess;
+}
+
+template <class T>
+int solve_impl(const Plan& P, const cx<double>* y, cx<double>* x, const gs_solve_opts& opt, gs_solve_info& info,
+               hipStream_t st) {
+    const int64_t nx = P.dim == 2 ? (int64_t)P.N * P.N : P.N;
+    const int64_t M = P.M;
+    Ops<T> o{P};
+    auto hipok = [&](hipError_t e) { return e == hipSuccess; };
+    double* hist = opt.history ? P.hist : nullptr;
+    const int hist_len = std::min(P.hist_len, opt.history_len);
+    hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, st, P.scal, (int)S_TOL2, opt.rel_tol * opt.rel_tol);
+    hipLaunchKernelGGL((init_b_kernel<T>), dim3(nb256(M)), dim3(256), 0, st, y, P.perm, P.smu64, M, P.b, P.r,
+                       o.rcopy());
+    if (!hipok(hipGetLastError())) return GS_ERR_HIP;
+    // reference ||A^H b|| (in apply precision T)
+    if (!hipok(launch_apply_TH<T>(P, o.ra(), o.sa(), AFLAGS, st))) return GS_ERR_HIP;
+    hipLaunchKernelGGL((norm2_partial_kernel<T>), dim3(RB), dim3(RT), 0, st, o.sa(), nx, P.red);
+    hipLaunchKernelGGL(start_scalars_kernel, dim3(1), dim3(RT), 0, st, P.scal, P.red, 1, nullptr, 0);
+    if (opt.warm_start) {
+        if (!hipok(compute_residual<T>(P, x, st))) return GS_ERR_HIP;
+    } else {
+        hipLaunchKernelGGL((zero_kernel<double>), dim3(nb256(nx)), dim3(256), 0, st, x, nx);
+    }
+    if (!hipok(cgls_start<T>(P, st, 0, hist, hist_len))) return GS_ERR_HIP;
+
+    bool done = false, broke = false;
+    int used = 0, restarts = 0;
+    double rel = -1, rel64 = -1;
+    if (!hipok(cgls_run<T>(P, x, st, opt.max_iter, std::max(1, opt.check_every), hist, hist_len, done, broke)))
+        return GS_ERR_HIP;
+    used = (int)P.host_scal[S_ITER];
+    rel = P.host_scal[S_REF] > 0 ? std::sqrt(P.host_scal[S_GAMMA]) / P.host_scal[S_REF] : 0.0;
+
+    const bool refine = opt.refine_fp64 && std::is_same<T, float>::value && P.d64.present;
+    if (refine && !broke) {
+        // FP64 reference ||A^H b|| and recomputed FP64 residual
+        if (!hipok(launch_apply_TH<double>(P, P.b, P.ss, AFLAGS, st))) return GS_ERR_HIP;
+        hipLaunchKernelGGL((norm2_partial_kernel<double>), dim3(RB), dim3(RT), 0, st, P.ss, nx, P.red);
+        hipLaunchKernelGGL(set_ref64_kernel, dim3(1), dim3(RT), 0, st, P.scal, P.red);
+        for (;;) {
+            if (!hipok(compute_residual<double>(P, x, st))) return GS_ERR_HIP;
+            if (!hipok(launch_apply_TH<double>(P, P.r, P.ss, AFLAGS, st))) return GS_ERR_HIP;
+            hipLaunchKernelGGL((norm2_partial_kernel<double>), dim3(RB), dim3(RT), 0, st, P.ss, nx, P.red);
+            std::vector<double> red(RB);
+            if (!hipok(hipMemcpyAsync(red.data(), P.red, RB * sizeof(double), hipMemcpyDeviceToHost, st)))
+                return GS_ERR_HIP;
+            if (!hipok(hipMemcpyAsync(P.host_scal, P.scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, st)))
+                return GS_ERR_HIP;
+            if (!hipok(hipStreamSynchronize(st))) return GS_ERR_HIP;
+            double g = 0;
+            for (double v : red) g += v;
+            const double ref64 = P.host_scal[S_REF64];
+            rel64 = ref64 > 0 ? std::sqrt(g) / ref64 : 0.0;
+            if (rel64 <= opt.rel_tol || restarts >= opt.max_restarts || used >= opt.max_iter) break;
+            ++restarts;
+            // restart the FP32 recurrence from x with the FP64 residual
+            hipLaunchKernelGGL((convert_kernel<T>), dim3(nb256(M)), dim3(256), 0, st, P.r, o.ra(), M);
+            if (!hipok(cgls_start<T>(P, st, 0, nullptr, 0))) return GS_ERR_HIP;
+            if (!hipok(cgls_run<T>(P, x, st, opt.max_iter - used, std::max(1, opt.check_every), nullptr, 0, done,
+                                   broke)))
+                return GS_ERR_HIP;
+            used += (int)P.host_scal[S_ITER];
+            rel = P.host_scal[S_REF] > 0 ? std::sqrt(P.host_scal[S_GAMMA]) / P.host_scal[S_REF] : 0.0;
+            if (broke) break;
+        }
+        done = rel64 <= opt.rel_tol;
+    }
+    if (opt.history && hist_len > 0) {
+        const int n = std::min(hist_len, used + 1);
+        if (!hipok(hipMemcpyAsync(opt.history, P.hist, n * sizeof(double), hipMemcpyDeviceToHost, st)))
+            return GS_ERR_HIP;
+    }
+    if (!hipok(hipStreamSynchronize(st))) return GS_ERR_HIP;
+    info.iterations = used;
+    info.restarts = restarts;
+    info.rel_residual = rel;
+    info.rel_residual_fp64 = rel64;
+    info.status = broke ? GS_ERR_BREAKDOWN : (done ? GS_OK : GS_NOT_CONVERGED);
+    return info.status;
+}
+
+}  // namespace gs
+
+extern "C" int gs_solve(const gs_plan_t* plan, const void* y, void* x, const gs_solve_opts* opts,
+                        gs_solve_info* info, void* stream);
+
+extern "C" int gs_solve(const gs_plan_t* plan, const void* y, void* x, const gs_solve_opts* opts, gs_solve_info* info,
+                        void* stream) {
+    if (!plan || !y || !x || !opts) return GS_ERR_INVALID_ARG;
+    if (!(opts->rel_tol >= 0) || opts->max_iter < 1 || opts->max_restarts < 0) return GS_ERR_INVALID_ARG;
+    if (opts->history && opts->history_len < 1) return GS_ERR_INVALID_ARG;
+    gs_solve_info local{};
+    gs_solve_info& inf = info ? *info : local;
+    inf = gs_solve_info{0, 0, GS_OK, -1.0, -1.0};
+    const gs::Plan& P = plan->impl;
+    hipStream_t st = (hipStream_t)stream;
+    if (P.d32.present && P.precision != GS_F64)
+        return gs::solve_impl<float>(P, (const gs::cx<double>*)y, (gs::cx<double>*)x, *opts, inf, st);
+    return gs::solve_impl<double>(P, (const gs::cx<double>*)y, (gs::cx<double>*)x, *opts, inf, st);
+}

@@ -1,0 +1,117 @@
+// Shared device/host definitions for libgs (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/gs.h"
+
+namespace gs {
+
+// ------------------------------------------------------------ complex math
+template <class T> struct alignas(2 * sizeof(T)) cx { T x, y; };
+template <class T> using C_t = cx<T>;
+
+// fixed-point position of the wrapped node eta' = frac(2^-J xi) in [0, 1)
+template <class T> struct posw;
+template <> struct posw<float> { using type = uint32_t; static constexpr int bits = 32; };
+template <> struct posw<double> { using type = uint64_t; static constexpr int bits = 64; };
+template <class T> using P_t = typename posw<T>::type;
+
+template <class T> __host__ __device__ inline cx<T> mk(T a, T b) { cx<T> c; c.x = a; c.y = b; return c; }
+template <class T> __host__ __device__ inline cx<T> cadd(cx<T> a, cx<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <class T> __host__ __device__ inline cx<T> csub(cx<T> a, cx<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <class T> __host__ __device__ inline cx<T> cmul(cx<T> a, cx<T> b) { return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+template <class T> __host__ __device__ inline cx<T> conjc(cx<T> a) { return mk<T>(a.x, -a.y); }
+template <class T> __host__ __device__ inline cx<T> cscale(cx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+template <class T> __host__ __device__ inline cx<T> cfma(cx<T> acc, cx<T> a, T s) { return mk<T>(acc.x + a.x * s, acc.y + a.y * s); }
+template <class T> __host__ __device__ inline cx<T> cmac(cx<T> acc, cx<T> a, cx<T> b) {  // acc + a*b
+    return mk<T>(acc.x + a.x * b.x - a.y * b.y, acc.y + a.x * b.y + a.y * b.x);
+}
+template <class T> __host__ __device__ inline cx<T> cmacc(cx<T> acc, cx<T> a, cx<T> b) {  // acc + conj(a)*b
+    return mk<T>(acc.x + a.x * b.x + a.y * b.y, acc.y + a.x * b.y - a.y * b.x);
+}
+template <class T> __host__ __device__ inline cx<T> czero() { return mk<T>(T(0), T(0)); }
+
+// ------------------------------------------------------------ plan
+// Window / NFFT parameters per precision.
+constexpr int W32 = 8, DEG32 = 7;     // FP32 path: 8 taps, degree-7 polynomial
+constexpr int W64 = 14, DEG64 = 13;   // FP64 path: 14 taps, degree-13 polynomial
+
+template <class T>
+struct PrecData {
+    using C = C_t<T>;
+    using P = P_t<T>;
+    bool present = false;
+    int w = 0, deg = 0;
+    P* pos = nullptr;      // [dim][M]
+    C* chx = nullptr;      // [nch][M]
+    C* chy = nullptr;      // [nch][M] (2D)
+    T* smu = nullptr;      // [M]
+    T* win = nullptr;      // [w][deg+1]
+    T* deap = nullptr;     // [N]: 1 / KB-hat((n - N/2)/ng), zero at boundary columns
+    C* tw = nullptr;       // [ng]: e^{-2 pi i k / ng}
+    // workspace
+    C* grid = nullptr;     // ng^dim (1D: four-step layout when ng > FFT_MAX_LDS)
+    C* sr = nullptr;       // [2nb][ng]  2D row-side grids (along y)
+    C* sc = nullptr;       // [2nb][ng]  2D col-side grids (along x)
+    C* part = nullptr;     // partial sums
+    C* vbuf = nullptr;     // [M] adjoint input in internal order (weighted)
+    C* ybuf = nullptr;     // [M] apply output in internal order (solver)
+    C* xbuf = nullptr;     // [N^dim] coefficient staging (solver)
+    size_t part_elems = 0;
+};
+
+constexpr int FFT_MAX_LDS = 4096;   // largest single-pass FFT held in LDS
+
+struct Plan {
+    int dim = 0, J = 0, p = 0, nb = 0, N = 0, precision = 0;
+    int64_t M = 0;
+    int ng = 0, G = 0;              // grid size per dim and log2
+    int n1 = 0, n2 = 0, lg1 = 0, lg2 = 0;   // four-step split (1D, ng > FFT_MAX_LDS)
+    int32_t* perm = nullptr;        // [M] internal -> caller index
+    int32_t* cell_start = nullptr;  // [ng^dim + 1] points sorted by cell (row-major)
+    PrecData<double> d64;
+    PrecData<float> d32;
+    // solver state (device; FP64 vectors in internal point order)
+    double* smu64 = nullptr;        // [M] sqrt(mu), internal order
+    cx<double> *b = nullptr, *r = nullptr, *q = nullptr;     // [M]
+    cx<double> *ps = nullptr, *ss = nullptr;                  // [N^dim]
+    cx<float> *q32 = nullptr, *r32 = nullptr;                 // [M]   FP32-apply operands
+    cx<float> *p32 = nullptr, *s32 = nullptr;                 // [N^dim]
+    double* red = nullptr;          // reduction partials [red_blocks]
+    double* scal = nullptr;         // device scalars
+    double* hist = nullptr;         // residual history (device)
+    double* host_scal = nullptr;    // pinned host mirror of scal
+    int red_blocks = 0, hist_len = 0;
+    int64_t bytes = 0;
+    std::string last_error;
+    hipStream_t upload_stream = nullptr;
+};
+
+template <class T> PrecData<T>& prec(Plan& p);
+template <> inline PrecData<double>& prec<double>(Plan& p) { return p.d64; }
+template <> inline PrecData<float>& prec<float>(Plan& p) { return p.d32; }
+template <class T> const PrecData<T>& prec(const Plan& p);
+template <> inline const PrecData<double>& prec<double>(const Plan& p) { return p.d64; }
+template <> inline const PrecData<float>& prec<float>(const Plan& p) { return p.d32; }
+
+// launch helpers (defined in nfft.hip / fft.hip)
+template <class T> hipError_t launch_apply_T(const Plan& P, const C_t<T>* x, C_t<T>* y, int flags, hipStream_t s);
+template <class T> hipError_t launch_apply_TH(const Plan& P, const C_t<T>* u, C_t<T>* x, int flags, hipStream_t s);
+
+inline int ilog2(int64_t v) { int l = 0; while ((int64_t(1) << l) < v) ++l; return l; }
+
+}  // namespace gs
+
+struct gs_plan {
+    gs::Plan impl;
+};
+
+#define GS_HIP_TRY(expr)                          \
+    do {                                          \
+        hipError_t _e = (expr);                   \
+        if (_e != hipSuccess) return _e;          \
+    } while (0)

@@ -1,0 +1,268 @@
+"""Thin ctypes binding of libgs.so (the C ABI declared in include/gs.h).
+
+Argument marshalling only: every step of T, T^H and the CGLS solve runs in the
+library's HIP kernels.  Device vectors are torch tensors on a ROCm device
+(complex128 for FP64 data, complex64 for FP32 data); host arrays are numpy.
+If the library is missing, importing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("GS_LIB", os.path.join(_HERE, "lib", "libgs.so"))
+
+GS_OK = 0
+GS_NOT_CONVERGED = 1
+GS_ERR_INVALID_ARG = -1
+GS_ERR_UNSUPPORTED = -2
+GS_ERR_BAD_NODES = -3
+GS_ERR_NOMEM = -4
+GS_ERR_HIP = -5
+GS_ERR_BREAKDOWN = -6
+GS_ERR_PRECISION = -7
+
+GS_F64, GS_F32, GS_F32_MIXED = 0, 1, 2
+GS_WEIGHTED, GS_SORTED, GS_APPLY_F64 = 1, 2, 4
+
+EXPORTS = [
+    "gs_plan", "gs_apply_T", "gs_apply_TH", "gs_solve", "gs_destroy", "gs_get_plan_info",
+    "gs_get_permutation", "gs_strerror", "gs_version", "gs_filter_taps", "gs_boundary_filters",
+    "gs_eval_basis_1d",
+]
+
+
+class GSError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} (code {code})")
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("rel_tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("warm_start", ctypes.c_int),
+                ("refine_fp64", ctypes.c_int), ("max_restarts", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("status", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("rel_residual_fp64", ctypes.c_double)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("J", ctypes.c_int), ("p", ctypes.c_int), ("N", ctypes.c_int),
+                ("precision", ctypes.c_int), ("M", ctypes.c_int64), ("grid_n", ctypes.c_int),
+                ("window_w32", ctypes.c_int), ("window_w64", ctypes.c_int), ("device_bytes", ctypes.c_int64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libgs.so not built ({LIB_PATH}); run python -m paper_1607_04091_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    lib.gs_plan.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i64, dp, dp, i32, vp]
+    lib.gs_apply_T.argtypes = [vp, vp, vp, i32, vp]
+    lib.gs_apply_TH.argtypes = [vp, vp, vp, i32, vp]
+    lib.gs_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
+    lib.gs_destroy.argtypes = [vp]
+    lib.gs_destroy.restype = None
+    lib.gs_get_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    lib.gs_get_permutation.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.gs_strerror.argtypes = [i32]
+    lib.gs_strerror.restype = ctypes.c_char_p
+    lib.gs_version.argtypes = []
+    lib.gs_filter_taps.argtypes = [i32, dp]
+    lib.gs_boundary_filters.argtypes = [i32, dp, dp, dp, dp, dp, dp]
+    lib.gs_eval_basis_1d.argtypes = [i32, i32, i64, dp, dp]
+    return lib
+
+
+_lib = _load()
+
+
+def library():
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return _lib.gs_strerror(int(code)).decode()
+
+
+def gs_version() -> int:
+    return _lib.gs_version()
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------ host-only queries
+
+def gs_filter_taps(p: int) -> np.ndarray:
+    h = np.zeros(2 * p)
+    rc = _lib.gs_filter_taps(p, _dptr(h))
+    if rc:
+        raise GSError(rc, "gs_filter_taps")
+    return h
+
+
+def gs_boundary_filters(p: int):
+    out = [np.zeros((p, p)), np.zeros((p, 2 * p - 1)), np.zeros(p),
+           np.zeros((p, p)), np.zeros((p, 2 * p - 1)), np.zeros(p)]
+    rc = _lib.gs_boundary_filters(p, *[_dptr(a) for a in out])
+    if rc:
+        raise GSError(rc, "gs_boundary_filters")
+    return {"U_left": out[0], "V_left": out[1], "v0_left": out[2],
+            "U_right": out[3], "V_right": out[4], "v0_right": out[5]}
+
+
+def gs_eval_basis_1d(J: int, p: int, xi) -> np.ndarray:
+    """(M, 2nb+1) complex128: [left boundary cols, D, right boundary cols]."""
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    nb = 0 if p == 1 else p
+    out = np.zeros((xi.size, 2 * nb + 1), dtype=np.complex128)
+    rc = _lib.gs_eval_basis_1d(J, p, xi.size, _dptr(xi), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc:
+        raise GSError(rc, "gs_eval_basis_1d")
+    return out
+
+
+# ------------------------------------------------------------------ plans
+
+def gs_plan(dim: int, J: int, p: int, xi, mu=None, precision: int = GS_F64, stream=None) -> "Plan":
+    """Build a plan (the paper's Freq2Wave init).  xi: (M,) or (M, 2) host array."""
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    M = xi.shape[0]
+    mu_a = None if mu is None else np.ascontiguousarray(mu, dtype=np.float64)
+    h = ctypes.c_void_p()
+    rc = _lib.gs_plan(ctypes.byref(h), dim, J, p, M, _dptr(xi),
+                      None if mu_a is None else _dptr(mu_a), precision,
+                      ctypes.c_void_p(0) if stream is None else _stream(stream))
+    if rc:
+        raise GSError(rc, "gs_plan")
+    return Plan(h, dim, J, p, M, precision)
+
+
+class Plan:
+    def __init__(self, handle, dim, J, p, M, precision):
+        self._h = handle
+        self.dim, self.J, self.p, self.M, self.precision = dim, J, p, M, precision
+        self.N = 1 << J
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("plan destroyed")
+        return self._h
+
+    def info(self) -> dict:
+        pi = PlanInfo()
+        rc = _lib.gs_get_plan_info(self.handle, ctypes.byref(pi))
+        if rc:
+            raise GSError(rc, "gs_get_plan_info")
+        return {f: getattr(pi, f) for f, _ in PlanInfo._fields_}
+
+    def permutation(self) -> np.ndarray:
+        out = np.zeros(self.M, dtype=np.int32)
+        rc = _lib.gs_get_permutation(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        if rc:
+            raise GSError(rc, "gs_get_permutation")
+        return out
+
+    def coef_shape(self):
+        return (self.N, self.N) if self.dim == 2 else (self.N,)
+
+    def _dtype(self, f64: bool):
+        import torch
+        use64 = self.precision == GS_F64 or f64
+        return torch.complex128 if use64 else torch.complex64
+
+    def apply_T(self, x, y=None, weighted=False, sorted_order=False, f64=False, stream=None):
+        import torch
+        dt = self._dtype(f64)
+        if x.dtype != dt or not x.is_contiguous() or x.numel() != self.N ** self.dim:
+            raise ValueError(f"x must be a contiguous {dt} tensor with {self.N ** self.dim} elements")
+        if y is None:
+            y = torch.empty(self.M, dtype=dt, device=x.device)
+        flags = (GS_WEIGHTED if weighted else 0) | (GS_SORTED if sorted_order else 0) | (GS_APPLY_F64 if f64 else 0)
+        rc = _lib.gs_apply_T(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), flags,
+                             _stream(stream))
+        if rc:
+            raise GSError(rc, "gs_apply_T")
+        return y
+
+    def apply_TH(self, u, x=None, weighted=False, sorted_order=False, f64=False, stream=None):
+        import torch
+        dt = self._dtype(f64)
+        if u.dtype != dt or not u.is_contiguous() or u.numel() != self.M:
+            raise ValueError(f"u must be a contiguous {dt} tensor with {self.M} elements")
+        if x is None:
+            x = torch.empty(self.coef_shape(), dtype=dt, device=u.device)
+        flags = (GS_WEIGHTED if weighted else 0) | (GS_SORTED if sorted_order else 0) | (GS_APPLY_F64 if f64 else 0)
+        rc = _lib.gs_apply_TH(self.handle, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(x.data_ptr()), flags,
+                              _stream(stream))
+        if rc:
+            raise GSError(rc, "gs_apply_TH")
+        return x
+
+    def solve(self, y, x=None, rel_tol=1e-6, max_iter=500, warm_start=False, refine_fp64=True, max_restarts=2,
+              check_every=1, history=False, stream=None):
+        import torch
+        if y.dtype != torch.complex128 or not y.is_contiguous() or y.numel() != self.M:
+            raise ValueError("y must be a contiguous complex128 tensor of length M")
+        if x is None:
+            if warm_start:
+                raise ValueError("warm_start needs x")
+            x = torch.zeros(self.coef_shape(), dtype=torch.complex128, device=y.device)
+        hist = np.zeros(max_iter + 1) if history else None
+        o = SolveOpts(rel_tol, max_iter, int(warm_start), int(refine_fp64), max_restarts, check_every,
+                      _dptr(hist) if hist is not None else None, hist.size if hist is not None else 0)
+        info = SolveInfo()
+        rc = _lib.gs_solve(self.handle, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                           ctypes.byref(o), ctypes.byref(info), _stream(stream))
+        if rc < 0:
+            raise GSError(rc, "gs_solve")
+        res = {"status": rc, "iterations": info.iterations, "restarts": info.restarts,
+               "rel_residual": info.rel_residual, "rel_residual_fp64": info.rel_residual_fp64}
+        if hist is not None:
+            res["history"] = hist[: info.iterations + 1].copy()
+        return x, res
+
+    def destroy(self):
+        if self._h:
+            _lib.gs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def gs_apply_T(plan: Plan, x, y=None, **kw):
+    return plan.apply_T(x, y, **kw)
+
+
+def gs_apply_TH(plan: Plan, u, x=None, **kw):
+    return plan.apply_TH(u, x, **kw)
+
+
+def gs_solve(plan: Plan, y, x=None, **kw):
+    return plan.solve(y, x, **kw)
+
+
+def gs_destroy(plan: Plan):
+    plan.destroy()

@@ -1,0 +1,185 @@
+"""Parity of the HIP T and T^H (through the C ABI) with the FP64 oracle's dense
+products, element by element, on seeded inputs.  Tolerances: relative error
+<= 1e-12 for FP64 applies and <= 2e-5 for FP32 applies."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import basis
+from workloads import grid, jitter_1d, spiral_2d, jitter_2d, voronoi_weights_1d, voronoi_weights_2d
+
+from gpu_util import rel, crandn, to_dev, to_host, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 2e-5}
+
+
+@pytest.fixture(scope="module")
+def gs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1607_04091_amd import gs as _gs
+    return _gs
+
+
+def _case_1d(J, p, M, kind, seed):
+    rng = np.random.default_rng(seed)
+    N = 1 << J
+    if kind == "uniform":
+        xi = grid(M, 0.5)
+        mu = None
+    elif kind == "jitter":
+        xi = jitter_1d(M, N / M * 2.0, seed)
+        mu = voronoi_weights_1d(xi, np.abs(xi).max() + 0.5)
+    else:  # random, beyond the band and with repeated points
+        xi = rng.uniform(-1.3 * N, 1.3 * N, M)
+        xi[:5] = xi[5]
+        mu = rng.uniform(0.1, 2.0, M)
+    return xi, mu
+
+
+ONE_D = [
+    # J, p, M, kind
+    (6, 2, 200, "random"),
+    (8, 2, 1024, "uniform"),      # C1 shape
+    (7, 4, 555, "jitter"),
+    (5, 1, 301, "random"),        # Haar
+    (9, 3, 1500, "random"),
+    (12, 4, 6000, "jitter"),      # grid 8192 > LDS limit: four-step FFT
+    (3, 4, 50, "random"),         # 2^J = 2p: no interior column
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("J,p,M,kind", ONE_D)
+def test_apply_1d(gs, J, p, M, kind, prec):
+    say(f"[apply_1d] J={J} p={p} M={M} {kind} prec={prec}")
+    xi, mu = _case_1d(J, p, M, kind, 1000 * J + p)
+    rng = np.random.default_rng(7 + J)
+    N = 1 << J
+    x = crandn(rng, N)
+    u = crandn(rng, M)
+    T = basis.dense_T_1d(xi, J, p)
+    plan = gs.gs_plan(1, J, p, xi, mu, precision=prec)
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    y = to_host(plan.apply_T(to_dev(x, dt)))
+    assert rel(y, T @ x) < TOL[prec]
+    z = to_host(plan.apply_TH(to_dev(u, dt)))
+    assert rel(z, T.conj().T @ u) < TOL[prec]
+    if mu is not None:
+        s = np.sqrt(mu)
+        yw = to_host(plan.apply_T(to_dev(x, dt), weighted=True))
+        assert rel(yw, s * (T @ x)) < TOL[prec]
+        zw = to_host(plan.apply_TH(to_dev(u, dt), weighted=True))
+        assert rel(zw, T.conj().T @ (s * u)) < TOL[prec]
+    plan.destroy()
+
+
+def _case_2d(J, p, kind, M, seed):
+    N = 1 << J
+    if kind == "spiral":
+        arms = 16
+        pts = spiral_2d(arms, max(1, M // arms), N / 2, 0.5 * 64 / arms)
+        mu = voronoi_weights_2d(pts, "disk", N / 2 + 0.25, 0.4)
+    elif kind == "jitter":
+        pts = jitter_2d(M, N / 2, seed)
+        mu = voronoi_weights_2d(pts, "square", N / 2, N / np.sqrt(M))
+    else:
+        rng = np.random.default_rng(seed)
+        pts = rng.uniform(-0.8 * N, 0.8 * N, (M, 2))
+        mu = rng.uniform(0.5, 1.5, M)
+    return pts, mu
+
+
+TWO_D = [
+    (4, 2, "random", 700),
+    (5, 4, "spiral", 3000),
+    (5, 1, "jitter", 2000),       # Haar
+    (6, 3, "jitter", 9000),
+    (3, 4, "random", 400),        # no interior
+    (6, 4, "random", 5000),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("J,p,kind,M", TWO_D)
+def test_apply_2d(gs, J, p, kind, M, prec):
+    say(f"[apply_2d] J={J} p={p} {kind} M={M} prec={prec}")
+    pts, mu = _case_2d(J, p, kind, M, 31 * J + p)
+    M = pts.shape[0]
+    N = 1 << J
+    rng = np.random.default_rng(11 + J)
+    X = crandn(rng, (N, N))
+    u = crandn(rng, M)
+    plan = gs.gs_plan(2, J, p, pts, mu, precision=prec)
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    y = to_host(plan.apply_T(to_dev(X, dt)))
+    assert rel(y, basis.apply_T_2d(pts, J, p, X)) < TOL[prec]
+    Z = to_host(plan.apply_TH(to_dev(u, dt)))
+    assert rel(Z, basis.apply_TH_2d(pts, J, p, u)) < TOL[prec]
+    s = np.sqrt(mu)
+    yw = to_host(plan.apply_T(to_dev(X, dt), weighted=True))
+    assert rel(yw, s * basis.apply_T_2d(pts, J, p, X)) < TOL[prec]
+    Zw = to_host(plan.apply_TH(to_dev(u, dt), weighted=True))
+    assert rel(Zw, basis.apply_TH_2d(pts, J, p, s * u)) < TOL[prec]
+    plan.destroy()
+
+
+def test_adjoint_identity_and_determinism(gs):
+    say("[adjoint/determinism]")
+    pts, mu = _case_2d(6, 4, "spiral", 8000, 3)
+    rng = np.random.default_rng(5)
+    X = crandn(rng, (64, 64))
+    u = crandn(rng, pts.shape[0])
+    for prec, tol in ((0, 1e-13), (1, 1e-6)):
+        plan = gs.gs_plan(2, 6, 4, pts, mu, precision=prec)
+        dt = torch.complex128 if prec == 0 else torch.complex64
+        Xd, ud = to_dev(X, dt), to_dev(u, dt)
+        y = to_host(plan.apply_T(Xd))
+        Z1 = plan.apply_TH(ud)
+        Z2 = plan.apply_TH(ud)
+        assert torch.equal(Z1, Z2)                         # bitwise reproducible, no atomics
+        lhs = np.vdot(u, y)
+        rhs = np.vdot(to_host(Z1), X)
+        assert abs(lhs - rhs) / (np.linalg.norm(u) * np.linalg.norm(y)) < tol
+        plan.destroy()
+
+
+def test_sorted_order_and_permutation(gs):
+    say("[sorted order]")
+    xi, mu = _case_1d(7, 2, 400, "random", 9)
+    plan = gs.gs_plan(1, 7, 2, xi, mu, precision=0)
+    perm = plan.permutation()
+    assert sorted(perm.tolist()) == list(range(400))
+    rng = np.random.default_rng(1)
+    x = to_dev(crandn(rng, 128), torch.complex128)
+    y = to_host(plan.apply_T(x))
+    ys = to_host(plan.apply_T(x, sorted_order=True))
+    assert np.array_equal(ys, y[perm])
+    u = crandn(rng, 400)
+    z1 = to_host(plan.apply_TH(to_dev(u, torch.complex128)))
+    z2 = to_host(plan.apply_TH(to_dev(u[perm], torch.complex128), sorted_order=True))
+    assert np.array_equal(z1, z2)
+    info = plan.info()
+    assert info["grid_n"] == 256 and info["window_w64"] > 0 and info["device_bytes"] > 0
+    plan.destroy()
+
+
+def test_mixed_plan_has_both_paths(gs):
+    say("[mixed plan]")
+    pts, mu = _case_2d(5, 2, "random", 1500, 4)
+    rng = np.random.default_rng(2)
+    X = crandn(rng, (32, 32))
+    plan = gs.gs_plan(2, 5, 2, pts, mu, precision=gs.GS_F32_MIXED)
+    ref = basis.apply_T_2d(pts, 5, 2, X)
+    y32 = to_host(plan.apply_T(to_dev(X, torch.complex64)))
+    y64 = to_host(plan.apply_T(to_dev(X, torch.complex128), f64=True))
+    assert rel(y32, ref) < 2e-5
+    assert rel(y64, ref) < 1e-12
+    plan32 = gs.gs_plan(2, 5, 2, pts, mu, precision=gs.GS_F32)
+    with pytest.raises(gs.GSError):
+        plan32.apply_T(to_dev(X, torch.complex128), f64=True)
+    plan.destroy()
+    plan32.destroy()
