@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Benchmark: T + T^H apply pairs per second on one MI355X.
+
+Workload: 2D db4 tensor basis at J = 9 (512 x 512 coefficients), 1,048,576
+Archimedean-spiral frequencies (64 arms x 16384, radius <= 256) with
+Voronoi-area weights; FP32 applies (the metric form), weighted operator
+A = W^{1/2} T as CGLS uses it, caller point order, inputs resident in HBM.
+
+One step = one apply pair y = A x, z = A^H u through the C ABI.  Also
+reported: FP64 apply pairs/s, per-kernel times (HIP events on the launch
+stream), the roofline of the dominant kernel, the plan ("init") time,
+wall time to relative normal residual 1e-6 for the plain FP64 and the
+FP32-mixed CGLS, and the FP64 CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# Algorithmic bytes per launch of each kernel (measurement
+# section): the bytes the method itself must move, c = bytes per complex,
+# r = bytes per real, pos = bytes per fixed-point coordinate.
+def algorithmic_bytes(name, M, N, ng, nb, c, r, pos):
+    nch = 2 * nb + 1
+    grid = ng * ng * c
+    side = 4 * nb * ng * c
+    if name == "interp2d":
+        # coordinates, sqrt(mu), both channel sets, permutation, y; grid + side grids once
+        return M * (2 * pos + r + 2 * nch * c + 4 + c) + grid + side
+    if name == "spread2d":
+        return M * (2 * pos + c) + grid + 4 * (ng * ng + 1)
+    if name == "side_rows_partial":
+        return M * (pos + c + (nb * 2 + 1) * c) + 4 * (ng * ng + 1)
+    if name == "side_cols_partial":
+        return M * (pos + c + (nb * 2 + 1) * c) + 4 * (ng * ng + 1)
+    if name == "adj_prep":
+        return M * (4 + c + r + 2 * c + c + c)
+    if name == "boundary_partial":
+        return M * (4 * nb * c + c)
+    if name in ("fft_rows_T",):
+        return N * N * c + (N // 2 * 2) * ng * c + 2 * nb * ng * c
+    if name in ("fft_cols_T", "fft_cols_TH"):
+        return (N + ng) * ng * c
+    if name in ("fft_rows_TH",):
+        return N * ng * c + N * N * c
+    return None
+
+
+def oracle_baseline(pts, mu, J, p, sample, M):
+    """FP64 oracle (dense per-dimension columns + BLAS) on a bounded sample:
+    one weighted T and one T^H over `sample` points, scaled to pairs/s for M."""
+    from oracle import basis
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(pts.shape[0], size=sample, replace=False))
+    P = pts[idx]
+    s = np.sqrt(mu[idx])
+    N = 1 << J
+    X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    u = rng.standard_normal(sample) + 1j * rng.standard_normal(sample)
+    t0 = time.perf_counter()
+    y = s * basis.apply_T_2d(P, J, p, X)
+    Z = basis.apply_TH_2d(P, J, p, s * u)
+    t = time.perf_counter() - t0
+    assert np.isfinite(y).all() and np.isfinite(Z).all()
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    return {"value": 1.0 / (t * M / sample), "unit": "pairs/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"one weighted T and one T^H over {sample} of the {M} points (FP64, dense per-dimension "
+                      f"columns + BLAS), {t:.2f} s, scaled linearly to all points"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=32768)
+    ap.add_argument("--arms", type=int, default=64)
+    ap.add_argument("--per-arm", type=int, default=16384)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the point-sharded design "
+              "is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1607_04091_amd import gs
+    from workloads import spiral_2d, voronoi_weights_2d, ellipse_phantom_params, phantom_cell_averages, \
+        relative_noise
+
+    if not torch.cuda.is_available():
+        log("no GPU available")
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    J, p = 9, 4
+    N = 1 << J
+    r_max = 256.0
+    t0 = time.time()
+    pts = spiral_2d(args.arms, args.per_arm, r_max, 0.5)
+    mu = voronoi_weights_2d(pts, "disk", r_max + 0.25, 0.4)
+    M = pts.shape[0]
+    x0 = phantom_cell_averages(ellipse_phantom_params(301), J).astype(np.complex128)
+    log(f"[bench] inputs: M={M} spiral points, Voronoi weights ({time.time() - t0:.1f} s)")
+
+    t0 = time.perf_counter()
+    plan = gs.gs_plan(2, J, p, pts, mu, precision=gs.GS_F32_MIXED)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
+    log(f"[bench] plan (init, FP32+FP64 data): {t_init:.2f} s, device bytes {plan.info()['device_bytes'] / 2**20:.0f} MiB")
+
+    rng = np.random.default_rng(5)
+    xs = torch.from_numpy(rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))).to(dev)
+    us = torch.from_numpy(rng.standard_normal(M) + 1j * rng.standard_normal(M)).to(dev)
+    x32, u32 = xs.to(torch.complex64), us.to(torch.complex64)
+    y32 = torch.empty(M, dtype=torch.complex64, device=dev)
+    z32 = torch.empty((N, N), dtype=torch.complex64, device=dev)
+    y64 = torch.empty(M, dtype=torch.complex128, device=dev)
+    z64 = torch.empty((N, N), dtype=torch.complex128, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def pair32():
+        plan.apply_T(x32, y32, weighted=True, stream=stream)
+        plan.apply_TH(u32, z32, weighted=True, stream=stream)
+
+    def pair64():
+        plan.apply_T(xs, y64, weighted=True, f64=True, stream=stream)
+        plan.apply_TH(us, z64, weighted=True, f64=True, stream=stream)
+
+    def timed(fn, steps, warm):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms32 = timed(pair32, args.steps, args.warmup)
+    log(f"[bench] FP32 pair: {ms32:.3f} ms -> {1000 / ms32:.1f} pairs/s")
+    ms64 = timed(pair64, max(3, args.steps // 5), 2)
+    log(f"[bench] FP64 pair: {ms64:.3f} ms -> {1000 / ms64:.1f} pairs/s")
+    assert torch.isfinite(torch.view_as_real(y32)).all() and torch.isfinite(torch.view_as_real(z32)).all()
+
+    # per-kernel times of the FP32 pair, HIP events on the launch stream
+    gs.gs_profile_enable(True)
+    nprof = max(5, min(args.steps, 20))
+    for _ in range(nprof):
+        pair32()
+    torch.cuda.synchronize()
+    prof = gs.gs_profile_read()
+    gs.gs_profile_enable(False)
+    kernels = {k: {"launches": n, "avg_us": 1000.0 * t / n} for k, (n, t) in prof.items()}
+    for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["avg_us"] * kv[1]["launches"]):
+        log(f"[bench]   {k:20s} {v['launches']:5d} launches  avg {v['avg_us']:9.2f} us")
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"] / nprof)
+    nb = p
+    ab = algorithmic_bytes(dom, M, N, 2 * N, nb, 8, 4, 4)
+    roof = None
+    if ab is not None:
+        ach = ab / (kernels[dom]["avg_us"] * 1e-6) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic_bytes_per_launch": int(ab), "avg_launch_us": round(kernels[dom]["avg_us"], 2)}
+
+    solve = {}
+    if not args.no_solve:
+        x0d = torch.from_numpy(x0).to(dev)
+        yclean = torch.empty(M, dtype=torch.complex128, device=dev)
+        plan.apply_T(x0d, yclean, f64=True, stream=stream)
+        torch.cuda.synchronize()
+        ynp = yclean.cpu().numpy()
+        y = torch.from_numpy(ynp + relative_noise(ynp, 1e-4, 302)).to(dev)
+        for name, prec in (("fp32_mixed", gs.GS_F32_MIXED), ("plain_fp64", gs.GS_F64)):
+            pl = plan if prec == gs.GS_F32_MIXED else gs.gs_plan(2, J, p, pts, mu, precision=prec)
+            xsol = torch.zeros((N, N), dtype=torch.complex128, device=dev)
+            pl.solve(y, xsol, rel_tol=1e-6, max_iter=2, check_every=1)     # warm-up of the code path
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xsol, info = pl.solve(y, xsol, rel_tol=1e-6, max_iter=1000, refine_fp64=True, max_restarts=3,
+                                  check_every=10)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            solve[name] = {"wall_s": round(dt, 4), "iterations": info["iterations"],
+                           "restarts": info["restarts"], "status": info["status"],
+                           "rel_residual": info["rel_residual"], "rel_residual_fp64": info["rel_residual_fp64"]}
+            log(f"[bench] solve {name}: {dt:.3f} s, {info['iterations']} iterations, status {info['status']}, "
+                f"rr {info['rel_residual']:.2e}, rr64 {info['rel_residual_fp64']:.2e}")
+            if pl is not plan:
+                pl.destroy()
+        solve["warm_start"] = None
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = oracle_baseline(pts, mu, J, p, min(args.cpu_sample, M), M)
+        log(f"[bench] oracle: {cpu['value']:.3e} pairs/s on {cpu['cores']} threads")
+
+    line = {
+        "metric": "T+T^H apply pairs/s (2D 512², 1M pts); time-to-rel-res 1e-6 plain vs warm-start",
+        "value": round(1000.0 / ms32, 2),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms32, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"2D db4 J=9 (512x512 coefficients), {M} Archimedean-spiral frequencies "
+                               f"({args.arms} arms, radius <= 256), Voronoi-area weights, weighted T and T^H, FP32",
+                   "points": M, "coefficients": N * N, "parallelism": "single GPU"},
+        "fp64_pairs_per_s": round(1000.0 / ms64, 2),
+        "init_s": round(t_init, 3),
+        "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()},
+        "roofline": roof,
+        "solve": solve,
+        "cpu_baseline": cpu,
+    }
+    plan.destroy()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

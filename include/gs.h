@@ -157,6 +157,18 @@ const char* gs_strerror(int code);
 int gs_version(void);
 
 /* ------------------------------------------------------------------------
+ * Per-kernel timing (measurement support).  gs_profile_enable(1) clears the
+ * record and makes every subsequent library kernel launch record a pair of
+ * HIP events on its launch stream; gs_profile_enable(0) stops recording (and
+ * clears).  gs_profile_read synchronizes on the recorded events and returns,
+ * per kernel that ran, its name (names[32*i], NUL-terminated), launch count
+ * and total elapsed milliseconds; *n_kernels receives the number of entries
+ * (<= max_kernels).  Process-wide; not for concurrent use from several threads.
+ * ------------------------------------------------------------------------ */
+int gs_profile_enable(int enable);
+int gs_profile_read(int max_kernels, char* names, int64_t* counts, double* total_ms, int* n_kernels);
+
+/* ------------------------------------------------------------------------
  * Host-only basis queries (no device work; usable without a GPU).
  * ------------------------------------------------------------------------ */
 

@@ -12,6 +12,9 @@
 
 #include "common.hpp"
 #include "host_math.hpp"
+#include "prof.hpp"
+
+#include <mutex>
 
 namespace gs {
 size_t adjoint_part_elems(int dim, int64_t M, int nb, int ng);
@@ -161,7 +164,48 @@ hipError_t upload_prec(gs::Plan& P, const HostPoints& H, const std::vector<doubl
 
 namespace gs {
 hipError_t solver_alloc(Plan& P);
+
+bool g_prof_enabled = false;
+
+namespace {
+struct ProfRec {
+    int id;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+std::vector<ProfRec> g_prof_recs;
+std::vector<size_t> g_prof_open;
+const char* const kKernelNames[K_COUNT] = {
+    "fft_rows_T", "fft_cols_T", "fft_sidecols_T", "interp2d", "interp1d", "fft1_T",
+    "adj_prep", "boundary_partial", "boundary_final", "spread2d", "side_rows_partial", "side_cols_partial",
+    "reduce_strips", "fft_cols_TH", "fft_rows_TH", "fft_sidecols_TH", "spread1d", "fft1_TH"};
+
+void prof_clear() {
+    for (auto& r : g_prof_recs) {
+        if (r.a) (void)hipEventDestroy(r.a);
+        if (r.b) (void)hipEventDestroy(r.b);
+    }
+    g_prof_recs.clear();
+    g_prof_open.clear();
 }
+}  // namespace
+
+void prof_record(int id, hipStream_t s, bool begin) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, s);
+    if (begin) {
+        g_prof_recs.push_back({id, e, nullptr});
+        g_prof_open.push_back(g_prof_recs.size() - 1);
+    } else if (!g_prof_open.empty()) {
+        g_prof_recs[g_prof_open.back()].b = e;
+        g_prof_open.pop_back();
+    } else {
+        (void)hipEventDestroy(e);
+    }
+}
+}  // namespace gs
 
 extern "C" {
 
@@ -345,6 +389,40 @@ int gs_get_permutation(const gs_plan_t* plan, int32_t* perm_host) {
     if (!plan || !perm_host) return GS_ERR_INVALID_ARG;
     hipError_t e = hipMemcpy(perm_host, plan->impl.perm, plan->impl.M * sizeof(int32_t), hipMemcpyDeviceToHost);
     return e == hipSuccess ? GS_OK : hip_fail(e);
+}
+
+int gs_profile_enable(int enable) {
+    std::lock_guard<std::mutex> lk(gs::g_prof_mu);
+    gs::prof_clear();
+    gs::g_prof_enabled = enable != 0;
+    return GS_OK;
+}
+
+int gs_profile_read(int max_kernels, char* names, int64_t* counts, double* total_ms, int* n_kernels) {
+    if (!names || !counts || !total_ms || !n_kernels || max_kernels < 1) return GS_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(gs::g_prof_mu);
+    int64_t cnt[gs::K_COUNT] = {0};
+    double tot[gs::K_COUNT] = {0};
+    for (auto& r : gs::g_prof_recs) {
+        if (!r.a || !r.b) continue;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return hip_fail(e);
+        float ms = 0;
+        e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return hip_fail(e);
+        cnt[r.id] += 1;
+        tot[r.id] += ms;
+    }
+    int n = 0;
+    for (int k = 0; k < gs::K_COUNT && n < max_kernels; ++k) {
+        if (!cnt[k]) continue;
+        std::snprintf(names + 32 * n, 32, "%s", gs::kKernelNames[k]);
+        counts[n] = cnt[k];
+        total_ms[n] = tot[k];
+        ++n;
+    }
+    *n_kernels = n;
+    return GS_OK;
 }
 
 int gs_filter_taps(int p, double* h) {

@@ -15,6 +15,7 @@
 
 #include "common.hpp"
 #include "fft.hpp"
+#include "prof.hpp"
 
 namespace gs {
 
@@ -482,6 +483,7 @@ template <class T, int NB>
 hipError_t launch_interp2d(const Plan& P, const Geo<T>& g, const cx<T>* x, cx<T>* y, int flags, hipStream_t s) {
     const PrecData<T>& d = prec<T>(P);
     constexpr int W = WinParams<T>::W, DEG = WinParams<T>::DEG;
+    ProfScope _p(K_INTERP2D, s);
     hipLaunchKernelGGL((interp2d_kernel<T, W, DEG, NB>), dim3(nblk(P.M, 256)), dim3(256), 0, s, g, d.grid, d.sr, d.sc,
                        x, y, flags);
     return hipGetLastError();
@@ -490,6 +492,7 @@ template <class T, int NB>
 hipError_t launch_interp1d(const Plan& P, const Geo<T>& g, const cx<T>* x, cx<T>* y, int flags, hipStream_t s) {
     const PrecData<T>& d = prec<T>(P);
     constexpr int W = WinParams<T>::W, DEG = WinParams<T>::DEG;
+    ProfScope _p(K_INTERP1D, s);
     hipLaunchKernelGGL((interp1d_kernel<T, W, DEG, NB>), dim3(nblk(P.M, 256)), dim3(256), 0, s, g, d.grid, x, y, flags);
     return hipGetLastError();
 }
@@ -522,25 +525,35 @@ hipError_t dispatch_interp(const Plan& P, const Geo<T>& g, const cx<T>* x, cx<T>
     return hipErrorInvalidValue;
 }
 
+#define GS_TIMED(id, ...)          \
+    do {                           \
+        ProfScope _p((id), s);     \
+        __VA_ARGS__;               \
+    } while (0)
+
 template <class T>
 hipError_t launch_apply_T(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hipStream_t s) {
     const PrecData<T>& d = prec<T>(P);
     const Geo<T> g = make_geo<T>(P);
     const int N = P.N, nb = P.nb, ng = P.ng;
     if (P.dim == 2) {
-        GS_HIP_TRY((launch_fft<T, -1>(OpT2Rows<T>{x, d.grid, d.sr, d.deap, N, nb, ng}, N, ng, 1, d.tw, ng, s)));
-        GS_HIP_TRY((launch_fft<T, -1>(OpCols<T>{d.grid, N, nb, ng, 1}, ng, ng, col_batch<T>(ng), d.tw, ng, s)));
+        GS_TIMED(K_FFT_ROWS_T, GS_HIP_TRY((launch_fft<T, -1>(OpT2Rows<T>{x, d.grid, d.sr, d.deap, N, nb, ng}, N, ng, 1,
+                                                           d.tw, ng, s))));
+        GS_TIMED(K_FFT_COLS_T, GS_HIP_TRY((launch_fft<T, -1>(OpCols<T>{d.grid, N, nb, ng, 1}, ng, ng,
+                                                           col_batch<T>(ng), d.tw, ng, s))));
         if (nb)
-            GS_HIP_TRY((launch_fft<T, -1>(OpT2SideCols<T>{x, d.sc, d.deap, N, nb, ng}, 2 * nb, ng, col_batch<T>(ng),
-                                          d.tw, ng, s)));
+            GS_TIMED(K_FFT_SIDECOLS_T,
+                     GS_HIP_TRY((launch_fft<T, -1>(OpT2SideCols<T>{x, d.sc, d.deap, N, nb, ng}, 2 * nb, ng,
+                                                   col_batch<T>(ng), d.tw, ng, s))));
     } else {
         const Pad1<T> pad{x, d.deap, N, ng};
         if (ng <= FFT_MAX_LDS) {
-            GS_HIP_TRY((launch_fft<T, -1>(OpT1Single<T>{pad, d.grid}, 1, ng, 1, d.tw, ng, s)));
+            GS_TIMED(K_FFT1_T, GS_HIP_TRY((launch_fft<T, -1>(OpT1Single<T>{pad, d.grid}, 1, ng, 1, d.tw, ng, s))));
         } else {
-            GS_HIP_TRY((launch_fft<T, -1>(OpT1A<T>{pad, d.grid, d.tw, P.n2, ng}, P.n2, P.n1, col_batch<T>(P.n1), d.tw,
-                                          ng, s)));
-            GS_HIP_TRY((launch_fft<T, -1>(OpRowsInPlace<T>{d.grid, P.n2}, P.n1, P.n2, 1, d.tw, ng, s)));
+            GS_TIMED(K_FFT1_T, GS_HIP_TRY((launch_fft<T, -1>(OpT1A<T>{pad, d.grid, d.tw, P.n2, ng}, P.n2, P.n1,
+                                                           col_batch<T>(P.n1), d.tw, ng, s))));
+            GS_TIMED(K_FFT1_T, GS_HIP_TRY((launch_fft<T, -1>(OpRowsInPlace<T>{d.grid, P.n2}, P.n1, P.n2, 1, d.tw,
+                                                           ng, s))));
         }
     }
     return dispatch_interp<T>(P, g, x, y, flags, s);
@@ -555,50 +568,61 @@ hipError_t launch_apply_TH(const Plan& P, const cx<T>* u, cx<T>* x, int flags, h
     cx<T>* v = d.vbuf;
     cx<T>* vI = d.part;  // first M entries of the partial buffer
     cx<T>* part = d.part + P.M;
-    hipLaunchKernelGGL((adj_prep_kernel<T>), dim3(nblk(P.M, 256)), dim3(256), 0, s, g, u, v, vI, flags);
+    GS_TIMED(K_ADJ_PREP, hipLaunchKernelGGL((adj_prep_kernel<T>), dim3(nblk(P.M, 256)), dim3(256), 0, s, g, u, v, vI,
+                                            flags));
     GS_HIP_TRY(hipGetLastError());
     const int nbl = nblk(P.M, BOUNDARY_CHUNK);
     if (nb) {
-        hipLaunchKernelGGL((boundary_partial_kernel<T>), dim3(nbl), dim3(256), 0, s, g, v, part, BOUNDARY_CHUNK);
+        GS_TIMED(K_BOUNDARY_PARTIAL, hipLaunchKernelGGL((boundary_partial_kernel<T>), dim3(nbl), dim3(256), 0, s, g, v,
+                                                        part, BOUNDARY_CHUNK));
         GS_HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL((boundary_final_kernel<T>), dim3(1), dim3(256), 0, s, g, part, nbl, x);
+        GS_TIMED(K_BOUNDARY_FINAL,
+                 hipLaunchKernelGGL((boundary_final_kernel<T>), dim3(1), dim3(256), 0, s, g, part, nbl, x));
         GS_HIP_TRY(hipGetLastError());
     }
     if (P.dim == 2) {
-        hipLaunchKernelGGL((spread2d_kernel<T, W, DEG>), dim3(nblk((int64_t)ng * ng, 256)), dim3(256), 0, s, g, vI,
-                           d.grid);
+        GS_TIMED(K_SPREAD2D, hipLaunchKernelGGL((spread2d_kernel<T, W, DEG>), dim3(nblk((int64_t)ng * ng, 256)),
+                                                dim3(256), 0, s, g, vI, d.grid));
         GS_HIP_TRY(hipGetLastError());
         if (nb) {
             const int strip = std::min(ng, 64);
             const int nstrip = ng / strip;
             const int count = 2 * nb * ng;
-            hipLaunchKernelGGL((side_rows_partial_kernel<T, W, DEG>), dim3(nblk((int64_t)nstrip * count, 256)),
-                               dim3(256), 0, s, g, v, part, strip);
+            GS_TIMED(K_SIDE_ROWS, hipLaunchKernelGGL((side_rows_partial_kernel<T, W, DEG>),
+                                                     dim3(nblk((int64_t)nstrip * count, 256)), dim3(256), 0, s, g, v,
+                                                     part, strip));
             GS_HIP_TRY(hipGetLastError());
-            hipLaunchKernelGGL((reduce_strips_kernel<T>), dim3(nblk(count, 256)), dim3(256), 0, s, part, d.sr, nstrip,
-                               count);
+            GS_TIMED(K_REDUCE_STRIPS, hipLaunchKernelGGL((reduce_strips_kernel<T>), dim3(nblk(count, 256)), dim3(256),
+                                                         0, s, part, d.sr, nstrip, count));
             GS_HIP_TRY(hipGetLastError());
-            hipLaunchKernelGGL((side_cols_partial_kernel<T, W, DEG>), dim3(nblk((int64_t)nstrip * count, 256)),
-                               dim3(256), 0, s, g, v, part, strip);
+            GS_TIMED(K_SIDE_COLS, hipLaunchKernelGGL((side_cols_partial_kernel<T, W, DEG>),
+                                                     dim3(nblk((int64_t)nstrip * count, 256)), dim3(256), 0, s, g, v,
+                                                     part, strip));
             GS_HIP_TRY(hipGetLastError());
-            hipLaunchKernelGGL((reduce_strips_kernel<T>), dim3(nblk(count, 256)), dim3(256), 0, s, part, d.sc, nstrip,
-                               count);
+            GS_TIMED(K_REDUCE_STRIPS, hipLaunchKernelGGL((reduce_strips_kernel<T>), dim3(nblk(count, 256)), dim3(256),
+                                                         0, s, part, d.sc, nstrip, count));
             GS_HIP_TRY(hipGetLastError());
         }
-        GS_HIP_TRY((launch_fft<T, +1>(OpCols<T>{d.grid, N, nb, ng, 0}, ng, ng, col_batch<T>(ng), d.tw, ng, s)));
-        GS_HIP_TRY((launch_fft<T, +1>(OpTH2Rows<T>{d.grid, d.sr, x, d.deap, N, nb, ng}, N, ng, 1, d.tw, ng, s)));
+        GS_TIMED(K_FFT_COLS_TH, GS_HIP_TRY((launch_fft<T, +1>(OpCols<T>{d.grid, N, nb, ng, 0}, ng, ng,
+                                                            col_batch<T>(ng), d.tw, ng, s))));
+        GS_TIMED(K_FFT_ROWS_TH, GS_HIP_TRY((launch_fft<T, +1>(OpTH2Rows<T>{d.grid, d.sr, x, d.deap, N, nb, ng}, N, ng,
+                                                            1, d.tw, ng, s))));
         if (nb)
-            GS_HIP_TRY((launch_fft<T, +1>(OpTH2SideCols<T>{d.sc, x, d.deap, N, nb, ng}, 2 * nb, ng, col_batch<T>(ng),
-                                          d.tw, ng, s)));
+            GS_TIMED(K_FFT_SIDECOLS_TH,
+                     GS_HIP_TRY((launch_fft<T, +1>(OpTH2SideCols<T>{d.sc, x, d.deap, N, nb, ng}, 2 * nb, ng,
+                                                   col_batch<T>(ng), d.tw, ng, s))));
     } else {
-        hipLaunchKernelGGL((spread1d_kernel<T, W, DEG>), dim3(nblk(ng, 256)), dim3(256), 0, s, g, vI, d.grid);
+        GS_TIMED(K_SPREAD1D, hipLaunchKernelGGL((spread1d_kernel<T, W, DEG>), dim3(nblk(ng, 256)), dim3(256), 0, s, g,
+                                                vI, d.grid));
         GS_HIP_TRY(hipGetLastError());
         const Crop1<T> crop{x, d.deap, N, nb, ng};
         if (ng <= FFT_MAX_LDS) {
-            GS_HIP_TRY((launch_fft<T, +1>(OpTH1Single<T>{d.grid, crop}, 1, ng, 1, d.tw, ng, s)));
+            GS_TIMED(K_FFT1_TH, GS_HIP_TRY((launch_fft<T, +1>(OpTH1Single<T>{d.grid, crop}, 1, ng, 1, d.tw, ng, s))));
         } else {
-            GS_HIP_TRY((launch_fft<T, +1>(OpTH1P1<T>{d.grid, d.tw, P.n2, ng}, P.n1, P.n2, 1, d.tw, ng, s)));
-            GS_HIP_TRY((launch_fft<T, +1>(OpTH1P2<T>{d.grid, crop, P.n2}, P.n2, P.n1, col_batch<T>(P.n1), d.tw, ng, s)));
+            GS_TIMED(K_FFT1_TH, GS_HIP_TRY((launch_fft<T, +1>(OpTH1P1<T>{d.grid, d.tw, P.n2, ng}, P.n1, P.n2, 1, d.tw,
+                                                            ng, s))));
+            GS_TIMED(K_FFT1_TH, GS_HIP_TRY((launch_fft<T, +1>(OpTH1P2<T>{d.grid, crop, P.n2}, P.n2, P.n1,
+                                                            col_batch<T>(P.n1), d.tw, ng, s))));
         }
     }
     return hipSuccess;

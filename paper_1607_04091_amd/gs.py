@@ -31,7 +31,7 @@ GS_WEIGHTED, GS_SORTED, GS_APPLY_F64 = 1, 2, 4
 EXPORTS = [
     "gs_plan", "gs_apply_T", "gs_apply_TH", "gs_solve", "gs_destroy", "gs_get_plan_info",
     "gs_get_permutation", "gs_strerror", "gs_version", "gs_filter_taps", "gs_boundary_filters",
-    "gs_eval_basis_1d",
+    "gs_eval_basis_1d", "gs_profile_enable", "gs_profile_read",
 ]
 
 
@@ -61,6 +61,10 @@ class PlanInfo(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libgs.so not built ({LIB_PATH}); run python -m paper_1607_04091_amd.build")
+    # torch ships its own HIP runtime with the same SONAME as the system one.
+    # Loading torch first makes libgs bind to that single runtime; loading
+    # libgs first would bring a second HIP/HSA runtime into the process.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
     lib.gs_plan.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i64, dp, dp, i32, vp]
@@ -77,6 +81,9 @@ def _load():
     lib.gs_filter_taps.argtypes = [i32, dp]
     lib.gs_boundary_filters.argtypes = [i32, dp, dp, dp, dp, dp, dp]
     lib.gs_eval_basis_1d.argtypes = [i32, i32, i64, dp, dp]
+    lib.gs_profile_enable.argtypes = [i32]
+    lib.gs_profile_read.argtypes = [i32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64), dp,
+                                    ctypes.POINTER(ctypes.c_int)]
     return lib
 
 
@@ -106,6 +113,32 @@ def _stream(stream):
     if isinstance(stream, int):
         return ctypes.c_void_p(stream)
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------ per-kernel timing
+
+def gs_profile_enable(enable: bool = True):
+    rc = _lib.gs_profile_enable(int(enable))
+    if rc:
+        raise GSError(rc, "gs_profile_enable")
+
+
+def gs_profile_read() -> dict:
+    """{kernel name: (launch count, total ms)} since the last enable."""
+    nmax = 64
+    names = ctypes.create_string_buffer(32 * nmax)
+    counts = (ctypes.c_int64 * nmax)()
+    tot = (ctypes.c_double * nmax)()
+    n = ctypes.c_int(0)
+    rc = _lib.gs_profile_read(nmax, names, counts, tot, ctypes.byref(n))
+    if rc:
+        raise GSError(rc, "gs_profile_read")
+    raw = names.raw
+    out = {}
+    for i in range(n.value):
+        nm = raw[32 * i:32 * (i + 1)].split(b"\0", 1)[0].decode()
+        out[nm] = (int(counts[i]), float(tot[i]))
+    return out
 
 
 # ------------------------------------------------------------------ host-only queries

@@ -5,7 +5,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from oracle import basis, lsq
-from workloads import config_c1, complex_noise, spiral_2d, voronoi_weights_2d, ellipse_phantom_params, \
+from workloads import config_c1, complex_noise, spiral_2d, jitter_2d, voronoi_weights_2d, ellipse_phantom_params, \
     phantom_cell_averages
 
 from gpu_util import rel, crandn, to_dev, to_host, say
@@ -42,19 +42,28 @@ def test_c1_solve_matches_lstsq(gs):
     plan.destroy()
 
 
-def _small_2d(J=5, p=4, arms=16, per_arm=250, seed=301):
+def _small_2d(J=5, p=4, pattern="spiral", seed=301):
+    """Well-conditioned 2D test problems.  A spiral of radius N/2 (the shape of
+    the 1M-point workload) leaves the corners of the coefficient band
+    unsampled and is numerically rank deficient (condition number ~1e9 at
+    J = 5), so least-squares parity uses a spiral of radius 0.75 N
+    (condition ~2e2) and a jittered grid over [-N, N]^2 (condition ~3)."""
     N = 1 << J
-    pts = spiral_2d(arms, per_arm, N / 2, 0.5 * 64 / arms)
-    mu = voronoi_weights_2d(pts, "disk", N / 2 + 0.25, 0.4)
+    if pattern == "spiral":
+        pts = spiral_2d(64, 140 * N // 32, 0.75 * N, 0.5)
+        mu = voronoi_weights_2d(pts, "disk", 0.75 * N + 0.25, 0.4)
+    else:
+        pts = jitter_2d(4 * N * N, N, seed)
+        mu = voronoi_weights_2d(pts, "square", N, 1.0)
     x0 = phantom_cell_averages(ellipse_phantom_params(seed), J).astype(complex)
     return pts, mu, x0
 
 
-@pytest.mark.parametrize("prec", [0, 2])
-def test_2d_weighted_solve_matches_lstsq(gs, prec):
-    say(f"[2d solve] prec={prec}")
+@pytest.mark.parametrize("pattern,prec", [("spiral", 0), ("jitter", 0), ("jitter", 2)])
+def test_2d_weighted_solve_matches_lstsq(gs, pattern, prec):
+    say(f"[2d solve] {pattern} prec={prec}")
     J, p = 5, 4
-    pts, mu, x0 = _small_2d(J, p)
+    pts, mu, x0 = _small_2d(J, p, pattern)
     T = basis.dense_T_2d(pts, J, p)
     y = T @ x0.reshape(-1)
     y = y + complex_noise(y.size, 1e-4 * np.linalg.norm(y) / np.sqrt(2 * y.size), 302)
@@ -69,8 +78,10 @@ def test_2d_weighted_solve_matches_lstsq(gs, prec):
         assert info["status"] == gs.GS_OK and err < 1e-6
     else:
         # FP32 applies + FP64 refinement: the FP64-recomputed normal residual
-        # meets the tolerance and the iterate is close to the LS solution
-        assert info["rel_residual_fp64"] <= tol * 1.0001
+        # meets the tolerance; with condition ~3 the iterate is within
+        # kappa^2 * tol of the LS solution
+        assert info["status"] == gs.GS_OK
+        assert info["rel_residual_fp64"] <= tol
         assert err < 1e-4
     plan.destroy()
 
@@ -78,7 +89,7 @@ def test_2d_weighted_solve_matches_lstsq(gs, prec):
 def test_warm_start_and_limits(gs):
     say("[warm start / limits]")
     J, p = 5, 2
-    pts, mu, x0 = _small_2d(J, p, seed=77)
+    pts, mu, x0 = _small_2d(J, p, "jitter", seed=77)
     T = basis.dense_T_2d(pts, J, p)
     y = T @ x0.reshape(-1)
     plan = gs.gs_plan(2, J, p, pts, mu, precision=0)
