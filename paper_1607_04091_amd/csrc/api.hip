@@ -178,7 +178,7 @@ std::vector<size_t> g_prof_open;
 const char* const kKernelNames[K_COUNT] = {
     "fft_rows_T", "fft_cols_T", "fft_sidecols_T", "interp2d", "interp1d", "fft1_T",
     "adj_prep", "boundary_partial", "boundary_final", "spread2d", "side_rows_partial", "side_cols_partial",
-    "reduce_strips", "fft_cols_TH", "fft_rows_TH", "fft_sidecols_TH", "spread1d", "fft1_TH"};
+    "reduce_strips", "fft_cols_TH", "fft_rows_TH", "fft_sidecols_TH", "spread1d", "fft1_TH", "merge_tiles"};
 
 void prof_clear() {
     for (auto& r : g_prof_recs) {
@@ -257,6 +257,7 @@ int gs_plan(gs_plan_t** out, int dim, int J, int p, int64_t M, const double* xi,
         P.lg1 = P.G; P.lg2 = 0;
     }
     P.n1 = 1 << P.lg1; P.n2 = 1 << P.lg2;
+    P.ts = std::min(gs::TILE, P.ng);
     hipStream_t s = (hipStream_t)stream;
 
     // ---- host math (FP64 / extended)
@@ -280,13 +281,13 @@ int gs_plan(gs_plan_t** out, int dim, int J, int p, int64_t M, const double* xi,
     std::vector<uint64_t> pos((size_t)dim * M);
     std::vector<int32_t> key(M);
     for (int64_t m = 0; m < M; ++m) {
-        int64_t k = 0;
+        int64_t cell[2] = {0, 0};
         for (int dm = 0; dm < dim; ++dm) {
             const uint64_t u = fixed_point_frac(xi[m * dim + dm], J);
             pos[(size_t)dm * M + m] = u;
-            k = (k << P.G) | (int64_t)(u >> (64 - P.G));
+            cell[dm] = (int64_t)(u >> (64 - P.G));
         }
-        key[m] = (int32_t)k;
+        key[m] = (int32_t)(dim == 2 ? gs::tile_key(cell[0], cell[1], P.ts, P.ng) : cell[0]);
     }
     // counting sort by cell (stable)
     const int64_t ncells = dim == 2 ? (int64_t)P.ng * P.ng : P.ng;

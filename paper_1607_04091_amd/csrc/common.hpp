@@ -65,11 +65,19 @@ struct PrecData {
 };
 
 constexpr int FFT_MAX_LDS = 4096;   // largest single-pass FFT held in LDS
+constexpr int TILE = 32;            // 2D point tiles: TILE x TILE grid cells
+
+// sort key of a 2D cell: tile-major (tiles of ts x ts cells), row-major inside a tile
+__host__ __device__ inline int64_t tile_key(int64_t cx, int64_t cy, int ts, int ng) {
+    const int64_t ntx = ng / ts;
+    return ((cx / ts) * ntx + (cy / ts)) * ts * ts + (cx % ts) * ts + (cy % ts);
+}
 
 struct Plan {
     int dim = 0, J = 0, p = 0, nb = 0, N = 0, precision = 0;
     int64_t M = 0;
     int ng = 0, G = 0;              // grid size per dim and log2
+    int ts = 0;                     // 2D tile side in cells (min(TILE, ng))
     int n1 = 0, n2 = 0, lg1 = 0, lg2 = 0;   // four-step split (1D, ng > FFT_MAX_LDS)
     int32_t* perm = nullptr;        // [M] internal -> caller index
     int32_t* cell_start = nullptr;  // [ng^dim + 1] points sorted by cell (row-major)

@@ -14,13 +14,42 @@ namespace gs {
 
 __device__ inline int bitrev(int i, int logn) { return logn ? (int)(__brev((unsigned)i) >> (32 - logn)) : 0; }
 
-// in-place radix-2 DIT on CB transforms buf[c*n + i], input in bit-reversed order.
-// tw[m] = e^{-2 pi i m / ng}; twstride = ng / n.
+// in-place decimation-in-time FFT on CB transforms buf[c*n + i], input in
+// bit-reversed order.  Two radix-2 stages are fused into one radix-4 pass
+// (one LDS round trip and one barrier per pair of stages); an odd stage count
+// ends with a radix-2 pass.  tw[m] = e^{-2 pi i m / ng}; twstride = ng / n.
 template <class T, int DIR>
 __device__ inline void lds_fft(cx<T>* buf, int n, int logn, int CB, const cx<T>* __restrict__ tw, int twstride) {
-    const int nbf = CB * (n >> 1);
-    for (int s = 1; s <= logn; ++s) {
+    int s = 1;
+    for (; s + 1 <= logn; s += 2) {
+        const int h = 1 << (s - 1);          // half length of the first fused stage
+        const int nq = CB * (n >> 2);        // radix-4 butterflies
+        __syncthreads();
+        for (int i = threadIdx.x; i < nq; i += blockDim.x) {
+            const int c = i >> (logn - 2);
+            const int j = i & ((n >> 2) - 1);
+            const int k = j & (h - 1);
+            const int grp = j >> (s - 1);
+            const int a = c * n + grp * 4 * h + k;
+            cx<T> w1 = tw[(k << (logn - s)) * twstride];          // e^{-2 pi i k / 2h}
+            cx<T> w2 = tw[(k << (logn - s - 1)) * twstride];      // e^{-2 pi i k / 4h}
+            if (DIR > 0) { w1.y = -w1.y; w2.y = -w2.y; }
+            const cx<T> x0 = buf[a], x1 = buf[a + h], x2 = buf[a + 2 * h], x3 = buf[a + 3 * h];
+            const cx<T> t1 = cmul(x1, w1), t3 = cmul(x3, w1);
+            const cx<T> y0 = cadd(x0, t1), y1 = csub(x0, t1), y2 = cadd(x2, t3), y3 = csub(x2, t3);
+            const cx<T> u2 = cmul(y2, w2);
+            // w3 = w2 * e^{-+ i pi/2}: multiply by -i (forward) or +i (adjoint)
+            cx<T> u3 = cmul(y3, w2);
+            u3 = (DIR > 0) ? mk<T>(-u3.y, u3.x) : mk<T>(u3.y, -u3.x);
+            buf[a] = cadd(y0, u2);
+            buf[a + 2 * h] = csub(y0, u2);
+            buf[a + h] = cadd(y1, u3);
+            buf[a + 3 * h] = csub(y1, u3);
+        }
+    }
+    if (s == logn) {                          // remaining radix-2 stage
         const int half = 1 << (s - 1);
+        const int nbf = CB * (n >> 1);
         __syncthreads();
         for (int i = threadIdx.x; i < nbf; i += blockDim.x) {
             const int c = i >> (logn - 1);
@@ -72,10 +101,10 @@ inline hipError_t launch_fft(const Op& op, int ntrans, int n, int CB, const cx<T
     return hipGetLastError();
 }
 
-// columns per workgroup for strided (column) passes: keep LDS <= 64 KB
+// columns per workgroup for strided (column) passes: keep LDS <= 32 KB
 template <class T>
 inline int col_batch(int n) {
-    int cb = (int)(65536 / ((size_t)n * sizeof(cx<T>)));
+    int cb = (int)(32768 / ((size_t)n * sizeof(cx<T>)));
     if (cb > 16) cb = 16;
     if (cb < 1) cb = 1;
     return cb;

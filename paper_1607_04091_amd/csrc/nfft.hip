@@ -19,6 +19,10 @@
 
 namespace gs {
 
+template <class T> hipError_t interp2d_tile(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hipStream_t s);
+template <class T> hipError_t adjoint2d_tile(const Plan& P, const cx<T>* u, cx<T>* x, int flags, hipStream_t s);
+size_t adjoint2d_part_elems(int ng, int ts, int nb, int w);
+
 // ------------------------------------------------------------------ helpers
 
 __device__ inline void decode_pos(uint32_t u, int G, int& cell, float& t) {
@@ -544,7 +548,7 @@ hipError_t launch_apply_T(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hi
         if (nb)
             GS_TIMED(K_FFT_SIDECOLS_T,
                      GS_HIP_TRY((launch_fft<T, -1>(OpT2SideCols<T>{x, d.sc, d.deap, N, nb, ng}, 2 * nb, ng,
-                                                   col_batch<T>(ng), d.tw, ng, s))));
+                                                   1, d.tw, ng, s))));
     } else {
         const Pad1<T> pad{x, d.deap, N, ng};
         if (ng <= FFT_MAX_LDS) {
@@ -556,6 +560,7 @@ hipError_t launch_apply_T(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hi
                                                            ng, s))));
         }
     }
+    if (P.dim == 2 && P.ts == TILE) return interp2d_tile<T>(P, x, y, flags, s);
     return dispatch_interp<T>(P, g, x, y, flags, s);
 }
 
@@ -565,6 +570,18 @@ hipError_t launch_apply_TH(const Plan& P, const cx<T>* u, cx<T>* x, int flags, h
     const Geo<T> g = make_geo<T>(P);
     constexpr int W = WinParams<T>::W, DEG = WinParams<T>::DEG;
     const int N = P.N, nb = P.nb, ng = P.ng;
+    if (P.dim == 2 && P.ts == TILE) {
+        GS_HIP_TRY(adjoint2d_tile<T>(P, u, x, flags, s));
+        GS_TIMED(K_FFT_COLS_TH, GS_HIP_TRY((launch_fft<T, +1>(OpCols<T>{d.grid, N, nb, ng, 0}, ng, ng,
+                                                            col_batch<T>(ng), d.tw, ng, s))));
+        GS_TIMED(K_FFT_ROWS_TH, GS_HIP_TRY((launch_fft<T, +1>(OpTH2Rows<T>{d.grid, d.sr, x, d.deap, N, nb, ng}, N, ng,
+                                                            1, d.tw, ng, s))));
+        if (nb)
+            GS_TIMED(K_FFT_SIDECOLS_TH,
+                     GS_HIP_TRY((launch_fft<T, +1>(OpTH2SideCols<T>{d.sc, x, d.deap, N, nb, ng}, 2 * nb, ng,
+                                                   1, d.tw, ng, s))));
+        return hipSuccess;
+    }
     cx<T>* v = d.vbuf;
     cx<T>* vI = d.part;  // first M entries of the partial buffer
     cx<T>* part = d.part + P.M;
@@ -610,7 +627,7 @@ hipError_t launch_apply_TH(const Plan& P, const cx<T>* u, cx<T>* x, int flags, h
         if (nb)
             GS_TIMED(K_FFT_SIDECOLS_TH,
                      GS_HIP_TRY((launch_fft<T, +1>(OpTH2SideCols<T>{d.sc, x, d.deap, N, nb, ng}, 2 * nb, ng,
-                                                   col_batch<T>(ng), d.tw, ng, s))));
+                                                   1, d.tw, ng, s))));
     } else {
         GS_TIMED(K_SPREAD1D, hipLaunchKernelGGL((spread1d_kernel<T, W, DEG>), dim3(nblk(ng, 256)), dim3(256), 0, s, g,
                                                 vI, d.grid));
@@ -642,7 +659,12 @@ size_t adjoint_part_elems(int dim, int64_t M, int nb, int ng) {
         const int strip = std::min(ng, 64);
         sides = (size_t)(ng / strip) * 2 * nb * ng;
     }
-    return need + std::max(b, sides) + 64;
+    size_t v1 = need + std::max(b, sides) + 64;
+    if (dim == 2) {
+        const int ts = std::min(TILE, ng);
+        v1 = std::max(v1, adjoint2d_part_elems(ng, ts, nb, std::max(W32, W64)));
+    }
+    return v1;
 }
 
 }  // namespace gs
