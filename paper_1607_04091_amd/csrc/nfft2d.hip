@@ -170,255 +170,409 @@ template <> struct Mfma<double> {
     __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 
-template <class T, int W, int NB, int CH>
-struct AdjLDS {
-    static constexpr int TS = TILE_TS, PW = TS + W - 1, NCH = 2 * NB, NRB = TS / TILE_RB;
-    static constexpr int NE = NB > 0 ? 4 * NB : 1;              // real entries of e (re/im of 2NB channels)
-    static constexpr int NBLK = (4 * NB + 15) / 16;              // 16x16 MFMA blocks per side
-    // staging
-    // column-side aggregation: thread (row, channel group), CPT channels each
-    static constexpr int CPT = NCH > 0 ? (NCH + 3) / 4 : 1;
-    static constexpr int NCP = NCH > 0 ? (NCH + CPT - 1) / CPT : 0;
-    // point index fastest for the arrays the gathering threads read
+// Row blocks and chunks.  A tile's points are split into NRB = TS/ADJ_RB row
+// blocks (ADJ_RB cell rows each, contiguous in the tile's order).  Chunk k
+// stages, for every row block b, its points k*CHB .. k*CHB+CHB-1 into LDS slots
+// b*CHB + i, so every row block (and every thread that owns outputs of it) gets
+// work in every chunk whatever the distribution of points over the rows.
+constexpr int ADJ_RB = 4;
+
+struct RbRange {
+    int lo, hi;   // tile-relative point range of row block b staged in this chunk
+};
+template <int CHB>
+__device__ inline RbRange rb_range(const int* off, int b, int k) {
+    constexpr int TS = TILE_TS, RB = ADJ_RB;
+    const int lo = off[b * RB * TS] + k * CHB;
+    return RbRange{lo, min(lo + CHB, off[(b + 1) * RB * TS])};
+}
+template <int CHB>
+__device__ inline int rb_chunks(const int* off) {
+    constexpr int TS = TILE_TS, RB = ADJ_RB, NRB = TS / RB;
+    int n = 0;
+    for (int b = 0; b < NRB; ++b) n = max(n, (off[(b + 1) * RB * TS] - off[b * RB * TS] + CHB - 1) / CHB);
+    return n;
+}
+template <int CHB>
+__device__ inline int rb_point(const int* off, int k, int s) {   // tile-relative point of slot s, or -1
+    constexpr int TS = TILE_TS, RB = ADJ_RB;
+    const int b = s / CHB, i = s - b * CHB;
+    const int p = off[b * RB * TS] + k * CHB + i;
+    return p < off[(b + 1) * RB * TS] ? p : -1;
+}
+
+// scaled input sample of sorted point q: sqrt(mu_q) u_q (weighted) or u_q
+template <class T>
+__device__ inline cx<T> adj_input(const TileGeo<T>& g, const cx<T>* __restrict__ u, int flags, int q) {
+    cx<T> v = u[(flags & GS_SORTED) ? q : g.perm[q]];
+    if (flags & GS_WEIGHTED) v = cscale(v, g.smu[q]);
+    return v;
+}
+
+// staged bytes per workgroup (two workgroups fit the 160 KB of LDS of a CU)
+constexpr int ADJ_LDS_BUDGET = 72 * 1024;
+constexpr int adj_chb(int slot_bytes, int nrb, int lo, int hi, int mult) {
+    int c = ADJ_LDS_BUDGET / (nrb * slot_bytes);
+    c = c > hi ? hi : c;
+    c -= c % mult;
+    return c < lo ? lo : c;
+}
+
+template <class T>
+struct alignas(16) AdjRec {
+    cx<T> v;   // conj(Dx Dy) sqrt(mu) u
+    int cy;    // tile-local cell column
+};
+
+template <class T, int W, int NB>
+struct AdjIntLDS {
+    static constexpr int TS = TILE_TS, PW = TS + W - 1, NRB = TS / ADJ_RB, NCH = 2 * NB;
+    static constexpr int SLOT = (int)(sizeof(AdjRec<T>) + 2 * W * sizeof(T) + NCH * sizeof(cx<T>));
+    static constexpr int CHB = adj_chb(SLOT, NRB, 8, 64, 2), CH = NRB * CHB;
     struct Stage {
-        int cy[CH];
-        cx<T> v[CH];
-        T wx[W][CH];
-        T wy[W][CH];
-        cx<T> cr[NCH > 0 ? NCH : 1][CH];
-        cx<T> dc[NCH > 0 ? NCH : 1][CH];
-        T e[CH][NE];
-        T f[CH][NE];
+        AdjRec<T> rec[CH];
+        T wx[CH][W];      // point-major so a thread reads a point's taps with wide loads
+        T wy[CH][W];
+        cx<T> cr[CH][NCH > 0 ? NCH : 1];   // conj(ax_r Dy) sqrt(mu) u: row-side values
     };
     struct Out {
         cx<T> P[PW][PW];
         cx<T> PR[NCH > 0 ? NCH : 1][PW];
-        cx<T> PC[NCH > 0 ? NCH : 1][PW];
     };
     static constexpr size_t bytes = sizeof(Stage) > sizeof(Out) ? sizeof(Stage) : sizeof(Out);
 };
 
-template <class T, int W, int DEG, int NB, int CH>
-__global__ void __launch_bounds__(384) adjoint_tile_kernel(TileGeo<T> g, const cx<T>* __restrict__ u, int flags,
-                                                           cx<T>* __restrict__ partI, cx<T>* __restrict__ partR,
-                                                           cx<T>* __restrict__ partC, cx<T>* __restrict__ partX) {
-    using L = AdjLDS<T, W, NB, CH>;
-    constexpr int TS = TILE_TS, RB = TILE_RB, PW = L::PW, NCH = L::NCH, NRB = L::NRB, NE = L::NE;
+template <int W>
+struct IntShape {
+    static constexpr int THREADS = ((TILE_TS + W - 1) * (TILE_TS / ADJ_RB) + 63) / 64 * 64;
+};
+
+// Interior spread and row sides of one tile.  Thread (ply, rb) owns padded
+// column ply for the output rows of row block rb (RB+W-1 register
+// accumulators) and the row-side sums PR[r][ply] of the block (the x-boundary
+// channels, spread along y); it gathers every point of the block whose cell
+// column lies in [ply-W+1, ply], reading each point once per column.
+template <class T, int W, int DEG, int NB>
+__global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(TileGeo<T> g, const cx<T>* __restrict__ u,
+                                                                            int flags, cx<T>* __restrict__ partI,
+                                                                            cx<T>* __restrict__ partR) {
+    using L = AdjIntLDS<T, W, NB>;
+    constexpr int TS = TILE_TS, RB = ADJ_RB, PW = L::PW, NRB = L::NRB, CH = L::CH, CHB = L::CHB, NCH = L::NCH;
     constexpr int NACC = RB + W - 1;
-    constexpr int NA = PW * NRB;                  // column-owner threads
-    constexpr int CPT = L::CPT, NCP = L::NCP;
-    constexpr int NBT = NB > 0 ? TS * NCP : 0;    // row-aggregation threads (row, channel group)
+    constexpr int NROUND = (NACC + RB - 1) / RB;   // row blocks b, b+NROUND write disjoint rows
+    constexpr int NTASK = NB > 0 ? 2 : 1;
+    constexpr int NTHR = IntShape<W>::THREADS;
     __shared__ int off[TS * TS + 1];
     __shared__ __attribute__((aligned(16))) unsigned char lds_raw[L::bytes];
-    __shared__ T cbuf[NB > 0 ? L::NBLK * L::NBLK * 256 : 1];
-    typename L::Stage& S = *reinterpret_cast<typename L::Stage*>(lds_raw);
+    auto& S = *reinterpret_cast<typename L::Stage*>(lds_raw);
 
-    const int tile = blockIdx.x;
-    const int tid = threadIdx.x;
+    const int tile = blockIdx.x, tid = threadIdx.x;
     const int kbase = tile << (2 * g.lts);
     const int q0 = g.cs[kbase];
-    const int cnt = g.cs[kbase + TS * TS] - q0;
     const int t0y = (tile % g.ntx) << g.lts;
-    for (int c = tid; c <= TS * TS; c += blockDim.x) off[c] = g.cs[kbase + c] - q0;
+    for (int c = tid; c <= TS * TS; c += NTHR) off[c] = g.cs[kbase + c] - q0;
+    __syncthreads();
+    const int nck = rb_chunks<CHB>(off);
     const size_t M = g.M;
-
-    // role A: (ply, rb); role B: (plx, half); role C: last wavefront (corners)
-    const bool roleA = tid < NA;
     const int ply = tid % PW, rb = tid / PW;
-    const bool roleB = NB > 0 && tid >= NA && tid < NA + NBT;
-    const int brow = (tid - NA) / (NCP > 0 ? NCP : 1), bcg = (tid - NA) % (NCP > 0 ? NCP : 1);
-    const int wave = tid >> 6, lane = tid & 63;
-    const bool roleC = NB > 0 && wave == (int)(blockDim.x >> 6) - 1;
+    const bool act = rb < NRB;
+    const int cy_lo = max(0, ply - (W - 1)), cy_hi = min(TS - 1, ply);
 
-    cx<T> accI[NACC];
-    cx<T> accR[NCH > 0 ? NCH : 1];
-    cx<T> accB[CPT][W];
+    cx<T> acc[NACC];
 #pragma unroll
-    for (int i = 0; i < NACC; ++i) accI[i] = czero<T>();
+    for (int i = 0; i < NACC; ++i) acc[i] = czero<T>();
+    cx<T> accR[NCH > 0 ? NCH : 1];
 #pragma unroll
     for (int i = 0; i < (NCH > 0 ? NCH : 1); ++i) accR[i] = czero<T>();
-#pragma unroll
-    for (int i = 0; i < CPT; ++i)
-#pragma unroll
-        for (int a = 0; a < W; ++a) accB[i][a] = czero<T>();
-    typename Mfma<T>::acc accM[L::NBLK * L::NBLK > 0 ? L::NBLK * L::NBLK : 1];
-#pragma unroll
-    for (int i = 0; i < (L::NBLK * L::NBLK > 0 ? L::NBLK * L::NBLK : 1); ++i) accM[i] = Mfma<T>::zero();
 
-    for (int c0 = 0; c0 < cnt; c0 += CH) {
-        const int c1 = min(cnt, c0 + CH);
-        __syncthreads();
-        // ---- stage: three tasks per point spread over the workgroup
-        for (int job = tid; job < 3 * CH; job += blockDim.x) {
-            const int t = job % CH, task = job / CH;
-            if (c0 + t >= c1) continue;
-            const int q = q0 + c0 + t;
-            cx<T> v = u[(flags & GS_SORTED) ? q : g.perm[q]];
-            if (flags & GS_WEIGHTED) v = cscale(v, g.smu[q]);
-            const cx<T> Dx = g.chx[NB * M + q], Dy = g.chy[NB * M + q];
+    for (int k = 0; k < nck; ++k) {
+        if (k) __syncthreads();
+        for (int job = tid; job < NTASK * CH; job += NTHR) {
+            const int task = job / CH, s = job - task * CH;
+            const int p = rb_point<CHB>(off, k, s);
+            if (p < 0) continue;
+            const int q = q0 + p;
+            const cx<T> v = adj_input(g, u, flags, q);
             if (task == 0) {
+                const cx<T> Dx = g.chx[NB * M + q], Dy = g.chy[NB * M + q];
                 int cxg, cyg;
                 T tx, ty;
                 decode_pos2(g.pos[q], g.G, cxg, tx);
                 decode_pos2(g.pos[M + q], g.G, cyg, ty);
-                S.cy[t] = cyg - t0y;
-                S.v[t] = cmul(conjc(cmul(Dx, Dy)), v);
+                AdjRec<T> r;
+                r.v = cmul(conjc(cmul(Dx, Dy)), v);
+                r.cy = cyg - t0y;
+                S.rec[s] = r;
                 T w[W];
                 taps_all<T, W, DEG>(tx, g.win, w);
 #pragma unroll
-                for (int j = 0; j < W; ++j) S.wx[j][t] = w[j];
+                for (int j = 0; j < W; ++j) S.wx[s][j] = w[j];
                 taps_all<T, W, DEG>(ty, g.win, w);
 #pragma unroll
-                for (int j = 0; j < W; ++j) S.wy[j][t] = w[j];
+                for (int j = 0; j < W; ++j) S.wy[s][j] = w[j];
             } else if constexpr (NB > 0) {
-                if (task == 1) {
+                const cx<T> vy = cmul(conjc(g.chy[NB * M + q]), v);
 #pragma unroll
-                    for (int r = 0; r < NCH; ++r) {
-                        const cx<T> ax = g.chx[(size_t)(r < NB ? r : r + 1) * M + q];
-                        S.cr[r][t] = cmul(conjc(cmul(ax, Dy)), v);
-                        const cx<T> e = cmul(conjc(ax), v);
-                        S.e[t][r] = e.x;
-                        S.e[t][NCH + r] = e.y;
-                    }
-                } else {
-#pragma unroll
-                    for (int r = 0; r < NCH; ++r) {
-                        const cx<T> ay = g.chy[(size_t)(r < NB ? r : r + 1) * M + q];
-                        S.dc[r][t] = cmul(conjc(cmul(ay, Dx)), v);
-                        S.f[t][r] = ay.x;
-                        S.f[t][NCH + r] = -ay.y;
-                    }
-                }
+                for (int r = 0; r < NCH; ++r) S.cr[s][r] = cmul(conjc(g.chx[(size_t)(r < NB ? r : r + 1) * M + q]), vy);
             }
         }
         __syncthreads();
-        if (roleA) {
-            const int cy_lo = max(0, ply - (W - 1)), cy_hi = min(TS - 1, ply);
-            if (cy_lo <= cy_hi) {
+        if (act) {
+            const RbRange R = rb_range<CHB>(off, rb, k);
+            const int sb = rb * CHB - R.lo;
 #pragma unroll
-                for (int rr = 0; rr < RB; ++rr) {
-                    const int cxl = rb * RB + rr;
-                    const int pa = max(off[cxl * TS + cy_lo], c0), pb = min(off[cxl * TS + cy_hi + 1], c1);
-                    for (int p = pa; p < pb; ++p) {
-                        const int t = p - c0;
-                        const int b = ply - S.cy[t];
-                        const T wyb = S.wy[b][t];
-                        const cx<T> tv = cscale(S.v[t], wyb);
+            for (int rr = 0; rr < RB; ++rr) {
+                const int row = rb * RB + rr;
+                const int pa = max(off[row * TS + cy_lo], R.lo), pb = min(off[row * TS + cy_hi + 1], R.hi);
+                auto point = [&](int t) {
+                    const AdjRec<T> r = S.rec[t];
+                    const T w = S.wy[t][ply - r.cy];
+                    T wx[W];
 #pragma unroll
-                        for (int a = 0; a < W; ++a) accI[rr + a] = cfma(accI[rr + a], tv, S.wx[a][t]);
-                        if constexpr (NB > 0) {
+                    for (int a = 0; a < W; ++a) wx[a] = S.wx[t][a];
+                    const cx<T> tv = cscale(r.v, w);
 #pragma unroll
-                            for (int r = 0; r < NCH; ++r) accR[r] = cfma(accR[r], S.cr[r][t], wyb);
-                        }
+                    for (int a = 0; a < W; ++a) acc[rr + a] = cfma(acc[rr + a], tv, wx[a]);
+                    if constexpr (NB > 0) {
+                        cx<T> cr[NCH];
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) cr[c] = S.cr[t][c];
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) accR[c] = cfma(accR[c], cr[c], w);
                     }
+                };
+                int p = pa;
+                for (; p + 1 < pb; p += 2) {
+                    point(sb + p);
+                    point(sb + p + 1);
                 }
-            }
-        } else if (roleB) {
-            if constexpr (NB > 0) {
-                // R[row][c][a] += d_c(m) wx_m[a] over the row's points (all lanes of a row read one point)
-                const int pa = max(off[brow * TS], c0), pb = min(off[brow * TS + TS], c1);
-                for (int p = pa; p < pb; ++p) {
-                    const int t = p - c0;
-                    T w[W];
-#pragma unroll
-                    for (int a = 0; a < W; ++a) w[a] = S.wx[a][t];
-#pragma unroll
-                    for (int k = 0; k < CPT; ++k) {
-                        const int c = bcg * CPT + k;
-                        if (c < NCH) {
-                            const cx<T> dv = S.dc[c][t];
-#pragma unroll
-                            for (int a = 0; a < W; ++a) accB[k][a] = cfma(accB[k][a], dv, w[a]);
-                        }
-                    }
-                }
-            }
-        } else if (roleC) {
-            if constexpr (NB > 0) {
-                const int i = lane & 15, kk = lane >> 4;
-                for (int k4 = c0; k4 < c1; k4 += 4) {
-                    const int p = k4 + kk;
-                    const bool ok = p < c1;
-#pragma unroll
-                    for (int bi = 0; bi < L::NBLK; ++bi) {
-                        const int ie = bi * 16 + i;
-                        const T av = (ok && ie < NE) ? S.e[p - c0][ie] : T(0);
-#pragma unroll
-                        for (int bj = 0; bj < L::NBLK; ++bj) {
-                            const int jf = bj * 16 + i;
-                            const T bv = (ok && jf < NE) ? S.f[p - c0][jf] : T(0);
-                            accM[bi * L::NBLK + bj] = Mfma<T>::step(av, bv, accM[bi * L::NBLK + bj]);
-                        }
-                    }
-                }
+                if (p < pb) point(sb + p);
             }
         }
     }
     __syncthreads();
-    // ---- combine the row blocks into the padded partial, one block per round (fixed order)
-    typename L::Out& O = *reinterpret_cast<typename L::Out*>(lds_raw);
-    for (int e = tid; e < PW * PW; e += blockDim.x) (&O.P[0][0])[e] = czero<T>();
-    if constexpr (NB > 0) {
-        for (int e = tid; e < NCH * PW; e += blockDim.x) (&O.PR[0][0])[e] = czero<T>();
-        for (int e = tid; e < NCH * PW; e += blockDim.x) (&O.PC[0][0])[e] = czero<T>();
-    }
+    auto& O = *reinterpret_cast<typename L::Out*>(lds_raw);
+    for (int e = tid; e < PW * PW; e += NTHR) (&O.P[0][0])[e] = czero<T>();
+    if constexpr (NB > 0)
+        for (int e = tid; e < NCH * PW; e += NTHR) (&O.PR[0][0])[e] = czero<T>();
     __syncthreads();
+    // row blocks overlap in W-1 output rows: add them in NROUND fixed rounds
+    for (int r = 0; r < NROUND; ++r) {
+        if (act && rb % NROUND == r) {
+#pragma unroll
+            for (int i = 0; i < NACC; ++i) O.P[rb * RB + i][ply] = cadd(O.P[rb * RB + i][ply], acc[i]);
+        }
+        __syncthreads();
+    }
     if constexpr (NB > 0) {
-        // column sides: C_c[plx] = sum_a R[plx - a][c][a]; rows with equal residue mod W
-        // touch disjoint outputs, so W rounds fold them without conflicts (fixed order)
-        for (int k = 0; k < W; ++k) {
-            if (roleB && brow % W == k) {
+        for (int r = 0; r < NRB; ++r) {
+            if (act && rb == r) {
 #pragma unroll
-                for (int kk = 0; kk < CPT; ++kk) {
-                    const int c = bcg * CPT + kk;
-                    if (c < NCH) {
-#pragma unroll
-                        for (int a = 0; a < W; ++a) O.PC[c][brow + a] = cadd(O.PC[c][brow + a], accB[kk][a]);
-                    }
-                }
+                for (int c = 0; c < NCH; ++c) O.PR[c][ply] = cadd(O.PR[c][ply], accR[c]);
             }
             __syncthreads();
         }
+        cx<T>* pR = partR + (size_t)tile * NCH * PW;
+        for (int e = tid; e < NCH * PW; e += NTHR) pR[e] = (&O.PR[0][0])[e];
     }
-    for (int b = 0; b < NRB; ++b) {
-        if (roleA && rb == b) {
+    cx<T>* pI = partI + (size_t)tile * PW * PW;
+    for (int e = tid; e < PW * PW; e += NTHR) pI[e] = (&O.P[0][0])[e];
+}
+
+template <class T, int W, int NB>
+struct AdjBndLDS {
+    static constexpr int TS = TILE_TS, PW = TS + W - 1, NRB = TS / ADJ_RB;
+    static constexpr int NCH = 2 * NB, NE = 4 * NB;          // channels; real entries of e, f
+    static constexpr int NBLK = (NE + 15) / 16;               // 16x16 MFMA blocks per side
+    static constexpr int SLOT = (int)(W * sizeof(T) + NCH * sizeof(cx<T>) + 2 * NE * sizeof(T));
+    static constexpr int CHB = adj_chb(SLOT, NRB, 4, 32, 4), CH = NRB * CHB;
+    struct Stage {
+        T wx[CH][W];
+        cx<T> dc[CH][NCH];   // conj(ay_c Dx) sqrt(mu) u: column-side values
+        T e[CH][NE];         // re / im of conj(ax_r) sqrt(mu) u
+        T f[CH][NE];         // re / -im of ay_c
+    };
+};
+
+// Column sides and corners of one tile (App. C, the remaining blocks of the
+// 2D matrix), with the same chunked staging as the interior kernel.
+//   waves [0, COLW):  column sides PC[c][x] = sum_m dc_c(m) wx_m[x - cx_m].  A
+//       wave sums, per cell row, B[c][a] = sum over the row's points of
+//       dc_c wx[a] with lane = (c, a), then adds B[c][a] to its own partial
+//       at (c, row + a).  All lanes walk the same points, so the work is
+//       balanced whatever the distribution of points.
+//   waves [COLW, COLW+CORW): corners sum_m conj(ax_r ay_c) sqrt(mu_m) u_m as a
+//       real 16x16 MFMA product over the chunk's slots.
+constexpr int BND_COLW = 4, BND_CORW = 2;
+constexpr int BND_THREADS = 64 * (BND_COLW + BND_CORW);
+
+template <class T, int W, int DEG, int NB>
+__global__ void __launch_bounds__(BND_THREADS) adj_boundary_kernel(TileGeo<T> g, const cx<T>* __restrict__ u, int flags,
+                                                                   cx<T>* __restrict__ partC, cx<T>* __restrict__ partX) {
+    using L = AdjBndLDS<T, W, NB>;
+    constexpr int TS = TILE_TS, RB = ADJ_RB, PW = L::PW, NRB = L::NRB, NCH = L::NCH, NE = L::NE;
+    constexpr int CH = L::CH, CHB = L::CHB;
+    constexpr int NBLK = L::NBLK, LD = 16 * NBLK;
+    constexpr int NPAIR = NCH * W, NPB = (NPAIR + 63) / 64;   // (channel, tap) lanes and their wave blocks
+    static_assert(NPB <= BND_COLW, "column-side lanes");
+    constexpr int RG = BND_COLW / NPB;                        // row-block groups
+    constexpr int NCHAIN = (NRB + RG - 1) / RG;               // row blocks per column-side wave
+    __shared__ int off[TS * TS + 1];
+    __shared__ __attribute__((aligned(16))) unsigned char lds_raw[sizeof(typename L::Stage)];
+    __shared__ cx<T> PCw[BND_COLW][NCH][PW];
+    __shared__ T cbuf[BND_CORW][LD * LD];
+    auto& S = *reinterpret_cast<typename L::Stage*>(lds_raw);
+
+    const int tile = blockIdx.x, tid = threadIdx.x;
+    const int kbase = tile << (2 * g.lts);
+    const int q0 = g.cs[kbase];
+    for (int c = tid; c <= TS * TS; c += BND_THREADS) off[c] = g.cs[kbase + c] - q0;
+    for (int e = tid; e < BND_COLW * NCH * PW; e += BND_THREADS) (&PCw[0][0][0])[e] = czero<T>();
+    __syncthreads();
+    const int nck = rb_chunks<CHB>(off);
+    const size_t M = g.M;
+    const int wave = tid >> 6, lane = tid & 63;
+    const bool colw = wave < BND_COLW;
+    // column-side lane roles
+    const int pb = wave % NPB, rg = wave / NPB;
+    const int pair = pb * 64 + lane;
+    const bool colact = colw && rg < RG && pair < NPAIR;
+    const int cc = pair / W, ca = pair - cc * W;
+    cx<T> accC[NCHAIN];
+    int cur[NCHAIN];
 #pragma unroll
-            for (int i = 0; i < NACC; ++i) O.P[b * RB + i][ply] = cadd(O.P[b * RB + i][ply], accI[i]);
-            if constexpr (NB > 0) {
+    for (int i = 0; i < NCHAIN; ++i) {
+        accC[i] = czero<T>();
+        cur[i] = -1;
+    }
+    // corner lane roles
+    const int cw = wave - BND_COLW;
+    const int li = lane & 15, kk = lane >> 4;
+    typename Mfma<T>::acc accM[NBLK * NBLK];
 #pragma unroll
-                for (int r = 0; r < NCH; ++r) O.PR[r][ply] = cadd(O.PR[r][ply], accR[r]);
+    for (int b = 0; b < NBLK * NBLK; ++b) accM[b] = Mfma<T>::zero();
+
+    for (int k = 0; k < nck; ++k) {
+        if (k) __syncthreads();
+        for (int job = tid; job < 3 * CH; job += BND_THREADS) {
+            const int task = job / CH, s = job - task * CH;
+            const int p = rb_point<CHB>(off, k, s);
+            if (p < 0) {
+                // empty slots enter the corner product as zeros
+                if (task == 1) {
+#pragma unroll
+                    for (int i = 0; i < NE; ++i) S.e[s][i] = T(0);
+                } else if (task == 2) {
+#pragma unroll
+                    for (int i = 0; i < NE; ++i) S.f[s][i] = T(0);
+                }
+                continue;
+            }
+            const int q = q0 + p;
+            if (task == 0) {
+                int cxg;
+                T tx;
+                decode_pos2(g.pos[q], g.G, cxg, tx);
+                T w[W];
+                taps_all<T, W, DEG>(tx, g.win, w);
+#pragma unroll
+                for (int j = 0; j < W; ++j) S.wx[s][j] = w[j];
+            } else if (task == 1) {
+                const cx<T> v = adj_input(g, u, flags, q);
+#pragma unroll
+                for (int r = 0; r < NCH; ++r) {
+                    const cx<T> e = cmul(conjc(g.chx[(size_t)(r < NB ? r : r + 1) * M + q]), v);
+                    S.e[s][r] = e.x;
+                    S.e[s][NCH + r] = e.y;
+                }
+            } else {
+                const cx<T> v = adj_input(g, u, flags, q);
+                const cx<T> vx = cmul(conjc(g.chx[NB * M + q]), v);
+#pragma unroll
+                for (int r = 0; r < NCH; ++r) {
+                    const cx<T> ay = g.chy[(size_t)(r < NB ? r : r + 1) * M + q];
+                    S.dc[s][r] = cmul(conjc(ay), vx);
+                    S.f[s][r] = ay.x;
+                    S.f[s][NCH + r] = -ay.y;
+                }
             }
         }
         __syncthreads();
-    }
-    cx<T>* pI = partI + (size_t)tile * PW * PW;
-    for (int e = tid; e < PW * PW; e += blockDim.x) pI[e] = (&O.P[0][0])[e];
-    if constexpr (NB > 0) {
-        cx<T>* pR = partR + (size_t)tile * NCH * PW;
-        for (int e = tid; e < NCH * PW; e += blockDim.x) pR[e] = (&O.PR[0][0])[e];
-        cx<T>* pC = partC + (size_t)tile * NCH * PW;
-        for (int e = tid; e < NCH * PW; e += blockDim.x) pC[e] = (&O.PC[0][0])[e];
-        if (roleC) {
-            // lane holds four rows of column lane%16 of each 16x16 block
+        if (colact) {
 #pragma unroll
-            for (int bi = 0; bi < L::NBLK; ++bi)
+            for (int i = 0; i < NCHAIN; ++i) {
+                const int b = rg + i * RG;
+                if (b >= NRB) continue;
+                const RbRange R = rb_range<CHB>(off, b, k);
+                const int sb = b * CHB - R.lo;
 #pragma unroll
-                for (int bj = 0; bj < L::NBLK; ++bj)
-#pragma unroll
-                    for (int vv = 0; vv < 4; ++vv) {
-                        const int row = bi * 16 + Mfma<T>::row(lane, vv), col = bj * 16 + (lane & 15);
-                        cbuf[row * (16 * L::NBLK) + col] = accM[bi * L::NBLK + bj][vv];
+                for (int rr = 0; rr < RB; ++rr) {
+                    const int row = b * RB + rr;
+                    const int pa = max(off[row * TS], R.lo), pe = min(off[row * TS + TS], R.hi);
+                    if (pa >= pe) continue;
+                    if (row != cur[i]) {
+                        if (cur[i] >= 0) PCw[wave][cc][cur[i] + ca] = cadd(PCw[wave][cc][cur[i] + ca], accC[i]);
+                        accC[i] = czero<T>();
+                        cur[i] = row;
                     }
+                    cx<T> s = accC[i];
+#pragma unroll 4
+                    for (int p = pa; p < pe; ++p) s = cfma(s, S.dc[sb + p][cc], S.wx[sb + p][ca]);
+                    accC[i] = s;
+                }
+            }
+        } else if (!colw) {
+            // C = E F^T over the chunk's slots, 4 slots per MFMA step
+            for (int s4 = cw; s4 < CH / 4; s4 += BND_CORW) {
+                const int t = 4 * s4 + kk;
+#pragma unroll
+                for (int bi = 0; bi < NBLK; ++bi) {
+                    const int ie = bi * 16 + li;
+                    const T av = ie < NE ? S.e[t][ie] : T(0);
+#pragma unroll
+                    for (int bj = 0; bj < NBLK; ++bj) {
+                        const int jf = bj * 16 + li;
+                        const T bv = jf < NE ? S.f[t][jf] : T(0);
+                        accM[bi * NBLK + bj] = Mfma<T>::step(av, bv, accM[bi * NBLK + bj]);
+                    }
+                }
+            }
         }
-        __syncthreads();
-        cx<T>* pX = partX + (size_t)tile * NCH * NCH;
-        constexpr int LD = 16 * L::NBLK;
-        for (int e = tid; e < NCH * NCH; e += blockDim.x) {
-            const int r = e / NCH, c = e - r * NCH;
-            const T re = cbuf[r * LD + c] - cbuf[(NCH + r) * LD + NCH + c];
-            const T im = cbuf[r * LD + NCH + c] + cbuf[(NCH + r) * LD + c];
-            pX[e] = mk<T>(re, im);
+    }
+    if (colact) {
+#pragma unroll
+        for (int i = 0; i < NCHAIN; ++i)
+            if (cur[i] >= 0) PCw[wave][cc][cur[i] + ca] = cadd(PCw[wave][cc][cur[i] + ca], accC[i]);
+    } else if (!colw) {
+#pragma unroll
+        for (int bi = 0; bi < NBLK; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < NBLK; ++bj)
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) {
+                    const int row = bi * 16 + Mfma<T>::row(lane, vv), col = bj * 16 + (lane & 15);
+                    cbuf[cw][row * LD + col] = accM[bi * NBLK + bj][vv];
+                }
+    }
+    __syncthreads();
+    // wave partials in fixed order
+    cx<T>* pC = partC + (size_t)tile * NCH * PW;
+    for (int e = tid; e < NCH * PW; e += BND_THREADS) {
+        cx<T> s = (&PCw[0][0][0])[e];
+#pragma unroll
+        for (int w = 1; w < BND_COLW; ++w) s = cadd(s, (&PCw[w][0][0])[e]);
+        pC[e] = s;
+    }
+    cx<T>* pX = partX + (size_t)tile * NCH * NCH;
+    for (int e = tid; e < NCH * NCH; e += BND_THREADS) {
+        const int r = e / NCH, c = e - r * NCH;
+        T re = T(0), im = T(0);
+#pragma unroll
+        for (int w = 0; w < BND_CORW; ++w) {
+            re += cbuf[w][r * LD + c] - cbuf[w][(NCH + r) * LD + NCH + c];
+            im += cbuf[w][r * LD + NCH + c] + cbuf[w][(NCH + r) * LD + c];
         }
+        pX[e] = mk<T>(re, im);
     }
 }
 
@@ -504,10 +658,8 @@ TileGeo<T> make_tile_geo(const Plan& P) {
 }
 
 template <class T> struct TileWin;
-template <> struct TileWin<float> { static constexpr int W = W32, DEG = DEG32, CH = 128; };
-template <> struct TileWin<double> { static constexpr int W = W64, DEG = DEG64, CH = 64; };
-// staging chunk: points per LDS refill (smaller for many boundary channels)
-template <class T, int NB> constexpr int tile_chunk() { return NB > 4 ? TileWin<T>::CH / 2 : TileWin<T>::CH; }
+template <> struct TileWin<float> { static constexpr int W = W32, DEG = DEG32; };
+template <> struct TileWin<double> { static constexpr int W = W64, DEG = DEG64; };
 
 template <class T, int NB>
 hipError_t interp2d_tile_nb(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hipStream_t s) {
@@ -524,7 +676,7 @@ template <class T, int NB>
 hipError_t adjoint2d_tile_nb(const Plan& P, const cx<T>* u, cx<T>* x, int flags, hipStream_t s) {
     const PrecData<T>& d = prec<T>(P);
     const TileGeo<T> g = make_tile_geo<T>(P);
-    constexpr int W = TileWin<T>::W, DEG = TileWin<T>::DEG, CH = tile_chunk<T, NB>();
+    constexpr int W = TileWin<T>::W, DEG = TileWin<T>::DEG;
     constexpr int PW = TILE_TS + W - 1;
     const int nt = g.ntx * g.ntx;
     const int nch = 2 * P.nb;
@@ -534,8 +686,14 @@ hipError_t adjoint2d_tile_nb(const Plan& P, const cx<T>* u, cx<T>* x, int flags,
     cx<T>* partX = partC + (size_t)nt * nch * PW;
     {
         ProfScope _p(K_SPREAD2D, s);
-        hipLaunchKernelGGL((adjoint_tile_kernel<T, W, DEG, NB, CH>), dim3(nt), dim3(384), 0, s, g, u, flags, partI,
-                           partR, partC, partX);
+        hipLaunchKernelGGL((adj_interior_kernel<T, W, DEG, NB>), dim3(nt), dim3(IntShape<W>::THREADS), 0, s, g, u,
+                           flags, partI, partR);
+        GS_HIP_TRY(hipGetLastError());
+    }
+    if constexpr (NB > 0) {
+        ProfScope _p(K_BND2D, s);
+        hipLaunchKernelGGL((adj_boundary_kernel<T, W, DEG, NB>), dim3(nt), dim3(BND_THREADS), 0, s, g, u, flags,
+                           partC, partX);
         GS_HIP_TRY(hipGetLastError());
     }
     {
