@@ -55,15 +55,26 @@ __device__ inline void decode_pos2(uint64_t u, int G, int& cell, double& t) {
     t = (double)(u & ((1ull << sh) - 1ull)) * __longlong_as_double((long long)(1023 - sh) << 52);
 }
 
+// W window taps at fractional offset t in [0, 1): tap j = phi(t + W/2 - 1 - j),
+// a degree-DEG polynomial p_j(x) in x = 2t - 1.  The window is even, so
+// p_{W-1-j}(x) = p_j(-x): only the first W/2 polynomials are read, each split
+// into even and odd parts in x^2, which gives both mirrored taps.
 template <class T, int W, int DEG>
 __device__ inline void taps_all(T t, const T* __restrict__ coef, T* w) {
-    const T x = T(2) * t - T(1);
+    static_assert(W % 2 == 0, "even window width");
+    constexpr int HE = DEG - (DEG & 1), HO = (DEG & 1) ? DEG : DEG - 1;
+    const T x = T(2) * t - T(1), y = x * x;
 #pragma unroll
-    for (int j = 0; j < W; ++j) {
-        T v = coef[j * (DEG + 1) + DEG];
+    for (int j = 0; j < W / 2; ++j) {
+        const T* c = coef + j * (DEG + 1);
+        T e = c[HE];
 #pragma unroll
-        for (int i = DEG - 1; i >= 0; --i) v = v * x + coef[j * (DEG + 1) + i];
-        w[j] = v;
+        for (int i = HE - 2; i >= 0; i -= 2) e = e * y + c[i];
+        T o = c[HO];
+#pragma unroll
+        for (int i = HO - 2; i >= 1; i -= 2) o = o * y + c[i];
+        w[j] = e + x * o;
+        w[W - 1 - j] = e - x * o;
     }
 }
 
@@ -201,12 +212,13 @@ __device__ inline int rb_point(const int* off, int k, int s) {   // tile-relativ
     return p < off[(b + 1) * RB * TS] ? p : -1;
 }
 
-// scaled input sample of sorted point q: sqrt(mu_q) u_q (weighted) or u_q
 template <class T>
-__device__ inline cx<T> adj_input(const TileGeo<T>& g, const cx<T>* __restrict__ u, int flags, int q) {
+__global__ void adj_gather_kernel(TileGeo<T> g, const cx<T>* __restrict__ u, int flags, cx<T>* __restrict__ vs) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= g.M) return;
     cx<T> v = u[(flags & GS_SORTED) ? q : g.perm[q]];
     if (flags & GS_WEIGHTED) v = cscale(v, g.smu[q]);
-    return v;
+    vs[q] = v;
 }
 
 // staged bytes per workgroup (two workgroups fit the 160 KB of LDS of a CU)
@@ -224,11 +236,17 @@ struct alignas(16) AdjRec {
     int cy;    // tile-local cell column
 };
 
+template <int W>
+struct IntShape {
+    static constexpr int THREADS = ((TILE_TS + W - 1) * (TILE_TS / ADJ_RB) + 63) / 64 * 64;
+};
+
 template <class T, int W, int NB>
 struct AdjIntLDS {
     static constexpr int TS = TILE_TS, PW = TS + W - 1, NRB = TS / ADJ_RB, NCH = 2 * NB;
     static constexpr int SLOT = (int)(sizeof(AdjRec<T>) + 2 * W * sizeof(T) + NCH * sizeof(cx<T>));
-    static constexpr int CHB = adj_chb(SLOT, NRB, 8, 64, 2), CH = NRB * CHB;
+    // at most one slot per thread: the next chunk's loads are held in registers
+    static constexpr int CHB = adj_chb(SLOT, NRB, 8, IntShape<W>::THREADS / NRB, 2), CH = NRB * CHB;
     struct Stage {
         AdjRec<T> rec[CH];
         T wx[CH][W];      // point-major so a thread reads a point's taps with wide loads
@@ -242,26 +260,31 @@ struct AdjIntLDS {
     static constexpr size_t bytes = sizeof(Stage) > sizeof(Out) ? sizeof(Stage) : sizeof(Out);
 };
 
-template <int W>
-struct IntShape {
-    static constexpr int THREADS = ((TILE_TS + W - 1) * (TILE_TS / ADJ_RB) + 63) / 64 * 64;
+// global data of one staged point, loaded a chunk ahead
+template <class T, int NB>
+struct IntPre {
+    int p;                       // tile-relative point, or -1 for an empty slot
+    P_t<T> px, py;
+    cx<T> v, dx, dy;
+    cx<T> ax[NB > 0 ? 2 * NB : 1];
 };
 
 // Interior spread and row sides of one tile.  Thread (ply, rb) owns padded
 // column ply for the output rows of row block rb (RB+W-1 register
 // accumulators) and the row-side sums PR[r][ply] of the block (the x-boundary
 // channels, spread along y); it gathers every point of the block whose cell
-// column lies in [ply-W+1, ply], reading each point once per column.
+// column lies in [ply-W+1, ply], reading each point once per column.  The
+// global loads of chunk k+1 are issued before chunk k is gathered.
 template <class T, int W, int DEG, int NB>
-__global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(TileGeo<T> g, const cx<T>* __restrict__ u,
-                                                                            int flags, cx<T>* __restrict__ partI,
+__global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(TileGeo<T> g, const cx<T>* __restrict__ vs,
+                                                                            cx<T>* __restrict__ partI,
                                                                             cx<T>* __restrict__ partR) {
     using L = AdjIntLDS<T, W, NB>;
     constexpr int TS = TILE_TS, RB = ADJ_RB, PW = L::PW, NRB = L::NRB, CH = L::CH, CHB = L::CHB, NCH = L::NCH;
     constexpr int NACC = RB + W - 1;
     constexpr int NROUND = (NACC + RB - 1) / RB;   // row blocks b, b+NROUND write disjoint rows
-    constexpr int NTASK = NB > 0 ? 2 : 1;
     constexpr int NTHR = IntShape<W>::THREADS;
+    static_assert(CH <= NTHR, "one slot per thread");
     __shared__ int off[TS * TS + 1];
     __shared__ __attribute__((aligned(16))) unsigned char lds_raw[L::bytes];
     auto& S = *reinterpret_cast<typename L::Stage*>(lds_raw);
@@ -278,6 +301,21 @@ __global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(Tile
     const bool act = rb < NRB;
     const int cy_lo = max(0, ply - (W - 1)), cy_hi = min(TS - 1, ply);
 
+    IntPre<T, NB> pre;
+    auto load = [&](int k) {
+        pre.p = tid < CH ? rb_point<CHB>(off, k, tid) : -1;
+        if (pre.p < 0) return;
+        const int q = q0 + pre.p;
+        pre.px = g.pos[q];
+        pre.py = g.pos[M + q];
+        pre.v = vs[q];
+        pre.dx = g.chx[NB * M + q];
+        pre.dy = g.chy[NB * M + q];
+#pragma unroll
+        for (int r = 0; r < NCH; ++r) pre.ax[r] = g.chx[(size_t)(r < NB ? r : r + 1) * M + q];
+    };
+    if (nck > 0) load(0);
+
     cx<T> acc[NACC];
 #pragma unroll
     for (int i = 0; i < NACC; ++i) acc[i] = czero<T>();
@@ -287,36 +325,31 @@ __global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(Tile
 
     for (int k = 0; k < nck; ++k) {
         if (k) __syncthreads();
-        for (int job = tid; job < NTASK * CH; job += NTHR) {
-            const int task = job / CH, s = job - task * CH;
-            const int p = rb_point<CHB>(off, k, s);
-            if (p < 0) continue;
-            const int q = q0 + p;
-            const cx<T> v = adj_input(g, u, flags, q);
-            if (task == 0) {
-                const cx<T> Dx = g.chx[NB * M + q], Dy = g.chy[NB * M + q];
-                int cxg, cyg;
-                T tx, ty;
-                decode_pos2(g.pos[q], g.G, cxg, tx);
-                decode_pos2(g.pos[M + q], g.G, cyg, ty);
-                AdjRec<T> r;
-                r.v = cmul(conjc(cmul(Dx, Dy)), v);
-                r.cy = cyg - t0y;
-                S.rec[s] = r;
-                T w[W];
-                taps_all<T, W, DEG>(tx, g.win, w);
+        if (pre.p >= 0) {
+            const int s = tid;
+            int cxg, cyg;
+            T tx, ty;
+            decode_pos2(pre.px, g.G, cxg, tx);
+            decode_pos2(pre.py, g.G, cyg, ty);
+            AdjRec<T> r;
+            r.v = cmul(conjc(cmul(pre.dx, pre.dy)), pre.v);
+            r.cy = cyg - t0y;
+            S.rec[s] = r;
+            T w[W];
+            taps_all<T, W, DEG>(tx, g.win, w);
 #pragma unroll
-                for (int j = 0; j < W; ++j) S.wx[s][j] = w[j];
-                taps_all<T, W, DEG>(ty, g.win, w);
+            for (int j = 0; j < W; ++j) S.wx[s][j] = w[j];
+            taps_all<T, W, DEG>(ty, g.win, w);
 #pragma unroll
-                for (int j = 0; j < W; ++j) S.wy[s][j] = w[j];
-            } else if constexpr (NB > 0) {
-                const cx<T> vy = cmul(conjc(g.chy[NB * M + q]), v);
+            for (int j = 0; j < W; ++j) S.wy[s][j] = w[j];
+            if constexpr (NB > 0) {
+                const cx<T> vy = cmul(conjc(pre.dy), pre.v);
 #pragma unroll
-                for (int r = 0; r < NCH; ++r) S.cr[s][r] = cmul(conjc(g.chx[(size_t)(r < NB ? r : r + 1) * M + q]), vy);
+                for (int c = 0; c < NCH; ++c) S.cr[s][c] = cmul(conjc(pre.ax[c]), vy);
             }
         }
         __syncthreads();
+        if (k + 1 < nck) load(k + 1);
         if (act) {
             const RbRange R = rb_range<CHB>(off, rb, k);
             const int sb = rb * CHB - R.lo;
@@ -324,7 +357,8 @@ __global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(Tile
             for (int rr = 0; rr < RB; ++rr) {
                 const int row = rb * RB + rr;
                 const int pa = max(off[row * TS + cy_lo], R.lo), pb = min(off[row * TS + cy_hi + 1], R.hi);
-                auto point = [&](int t) {
+                for (int p = pa; p < pb; ++p) {
+                    const int t = sb + p;
                     const AdjRec<T> r = S.rec[t];
                     const T w = S.wy[t][ply - r.cy];
                     T wx[W];
@@ -340,13 +374,7 @@ __global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(Tile
 #pragma unroll
                         for (int c = 0; c < NCH; ++c) accR[c] = cfma(accR[c], cr[c], w);
                     }
-                };
-                int p = pa;
-                for (; p + 1 < pb; p += 2) {
-                    point(sb + p);
-                    point(sb + p + 1);
                 }
-                if (p < pb) point(sb + p);
             }
         }
     }
@@ -379,21 +407,6 @@ __global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(Tile
     for (int e = tid; e < PW * PW; e += NTHR) pI[e] = (&O.P[0][0])[e];
 }
 
-template <class T, int W, int NB>
-struct AdjBndLDS {
-    static constexpr int TS = TILE_TS, PW = TS + W - 1, NRB = TS / ADJ_RB;
-    static constexpr int NCH = 2 * NB, NE = 4 * NB;          // channels; real entries of e, f
-    static constexpr int NBLK = (NE + 15) / 16;               // 16x16 MFMA blocks per side
-    static constexpr int SLOT = (int)(W * sizeof(T) + NCH * sizeof(cx<T>) + 2 * NE * sizeof(T));
-    static constexpr int CHB = adj_chb(SLOT, NRB, 4, 32, 4), CH = NRB * CHB;
-    struct Stage {
-        T wx[CH][W];
-        cx<T> dc[CH][NCH];   // conj(ay_c Dx) sqrt(mu) u: column-side values
-        T e[CH][NE];         // re / im of conj(ax_r) sqrt(mu) u
-        T f[CH][NE];         // re / -im of ay_c
-    };
-};
-
 // Column sides and corners of one tile (App. C, the remaining blocks of the
 // 2D matrix), with the same chunked staging as the interior kernel.
 //   waves [0, COLW):  column sides PC[c][x] = sum_m dc_c(m) wx_m[x - cx_m].  A
@@ -406,12 +419,39 @@ struct AdjBndLDS {
 constexpr int BND_COLW = 4, BND_CORW = 2;
 constexpr int BND_THREADS = 64 * (BND_COLW + BND_CORW);
 
+template <class T, int W, int NB>
+struct AdjBndLDS {
+    static constexpr int TS = TILE_TS, PW = TS + W - 1, NRB = TS / ADJ_RB;
+    static constexpr int NCH = 2 * NB, NE = 4 * NB;          // channels; real entries of e, f
+    static constexpr int NBLK = (NE + 15) / 16;               // 16x16 MFMA blocks per side
+    static constexpr int SLOT = (int)(W * sizeof(T) + NCH * sizeof(cx<T>) + 2 * NE * sizeof(T));
+    // two threads per slot
+    static constexpr int CHB = adj_chb(SLOT, NRB, 4, 24, 4), CH = NRB * CHB;
+    struct Stage {
+        T wx[CH][W];
+        cx<T> dc[CH][NCH];   // conj(ay_c Dx) sqrt(mu) u: column-side values
+        T e[CH][NE];         // re / im of conj(ax_r) sqrt(mu) u
+        T f[CH][NE];         // re / -im of ay_c
+    };
+};
+
+// global data of one staged point, loaded a chunk ahead, split over two
+// threads: half 0 takes the x coordinate and x channels, half 1 the y channels
+template <class T, int NB>
+struct BndPre {
+    int p;
+    P_t<T> px;
+    cx<T> v, d;
+    cx<T> ch[2 * NB];
+};
+
 template <class T, int W, int DEG, int NB>
-__global__ void __launch_bounds__(BND_THREADS) adj_boundary_kernel(TileGeo<T> g, const cx<T>* __restrict__ u, int flags,
+__global__ void __launch_bounds__(BND_THREADS) adj_boundary_kernel(TileGeo<T> g, const cx<T>* __restrict__ vs,
                                                                    cx<T>* __restrict__ partC, cx<T>* __restrict__ partX) {
     using L = AdjBndLDS<T, W, NB>;
     constexpr int TS = TILE_TS, RB = ADJ_RB, PW = L::PW, NRB = L::NRB, NCH = L::NCH, NE = L::NE;
     constexpr int CH = L::CH, CHB = L::CHB;
+    static_assert(2 * CH <= BND_THREADS, "one half slot per thread");
     constexpr int NBLK = L::NBLK, LD = 16 * NBLK;
     constexpr int NPAIR = NCH * W, NPB = (NPAIR + 63) / 64;   // (channel, tap) lanes and their wave blocks
     static_assert(NPB <= BND_COLW, "column-side lanes");
@@ -452,52 +492,59 @@ __global__ void __launch_bounds__(BND_THREADS) adj_boundary_kernel(TileGeo<T> g,
 #pragma unroll
     for (int b = 0; b < NBLK * NBLK; ++b) accM[b] = Mfma<T>::zero();
 
+    BndPre<T, NB> pre;
+    const int half = tid >= CH, hs = tid - half * CH;   // slot hs, half 0 or 1
+    auto load = [&](int k) {
+        pre.p = hs < CH ? rb_point<CHB>(off, k, hs) : -1;
+        if (pre.p < 0) return;
+        const int q = q0 + pre.p;
+        pre.v = vs[q];
+        if (half == 0) {
+            pre.px = g.pos[q];
+#pragma unroll
+            for (int r = 0; r < NCH; ++r) pre.ch[r] = g.chx[(size_t)(r < NB ? r : r + 1) * M + q];
+        } else {
+            pre.d = g.chx[NB * M + q];
+#pragma unroll
+            for (int r = 0; r < NCH; ++r) pre.ch[r] = g.chy[(size_t)(r < NB ? r : r + 1) * M + q];
+        }
+    };
+    if (nck > 0) load(0);
+
     for (int k = 0; k < nck; ++k) {
         if (k) __syncthreads();
-        for (int job = tid; job < 3 * CH; job += BND_THREADS) {
-            const int task = job / CH, s = job - task * CH;
-            const int p = rb_point<CHB>(off, k, s);
-            if (p < 0) {
+        if (hs < CH) {
+            const int s = hs;
+            if (pre.p < 0) {
                 // empty slots enter the corner product as zeros
-                if (task == 1) {
 #pragma unroll
-                    for (int i = 0; i < NE; ++i) S.e[s][i] = T(0);
-                } else if (task == 2) {
-#pragma unroll
-                    for (int i = 0; i < NE; ++i) S.f[s][i] = T(0);
-                }
-                continue;
-            }
-            const int q = q0 + p;
-            if (task == 0) {
+                for (int i = 0; i < NE; ++i) (half == 0 ? S.e[s][i] : S.f[s][i]) = T(0);
+            } else if (half == 0) {
                 int cxg;
                 T tx;
-                decode_pos2(g.pos[q], g.G, cxg, tx);
+                decode_pos2(pre.px, g.G, cxg, tx);
                 T w[W];
                 taps_all<T, W, DEG>(tx, g.win, w);
 #pragma unroll
                 for (int j = 0; j < W; ++j) S.wx[s][j] = w[j];
-            } else if (task == 1) {
-                const cx<T> v = adj_input(g, u, flags, q);
 #pragma unroll
                 for (int r = 0; r < NCH; ++r) {
-                    const cx<T> e = cmul(conjc(g.chx[(size_t)(r < NB ? r : r + 1) * M + q]), v);
+                    const cx<T> e = cmul(conjc(pre.ch[r]), pre.v);
                     S.e[s][r] = e.x;
                     S.e[s][NCH + r] = e.y;
                 }
             } else {
-                const cx<T> v = adj_input(g, u, flags, q);
-                const cx<T> vx = cmul(conjc(g.chx[NB * M + q]), v);
+                const cx<T> vx = cmul(conjc(pre.d), pre.v);
 #pragma unroll
                 for (int r = 0; r < NCH; ++r) {
-                    const cx<T> ay = g.chy[(size_t)(r < NB ? r : r + 1) * M + q];
-                    S.dc[s][r] = cmul(conjc(ay), vx);
-                    S.f[s][r] = ay.x;
-                    S.f[s][NCH + r] = -ay.y;
+                    S.dc[s][r] = cmul(conjc(pre.ch[r]), vx);
+                    S.f[s][r] = pre.ch[r].x;
+                    S.f[s][NCH + r] = -pre.ch[r].y;
                 }
             }
         }
         __syncthreads();
+        if (k + 1 < nck) load(k + 1);
         if (colact) {
 #pragma unroll
             for (int i = 0; i < NCHAIN; ++i) {
@@ -685,15 +732,20 @@ hipError_t adjoint2d_tile_nb(const Plan& P, const cx<T>* u, cx<T>* x, int flags,
     cx<T>* partC = partR + (size_t)nt * nch * PW;
     cx<T>* partX = partC + (size_t)nt * nch * PW;
     {
+        ProfScope _p(K_ADJ_PREP, s);
+        hipLaunchKernelGGL((adj_gather_kernel<T>), dim3((P.M + 255) / 256), dim3(256), 0, s, g, u, flags, d.vbuf);
+        GS_HIP_TRY(hipGetLastError());
+    }
+    {
         ProfScope _p(K_SPREAD2D, s);
-        hipLaunchKernelGGL((adj_interior_kernel<T, W, DEG, NB>), dim3(nt), dim3(IntShape<W>::THREADS), 0, s, g, u,
-                           flags, partI, partR);
+        hipLaunchKernelGGL((adj_interior_kernel<T, W, DEG, NB>), dim3(nt), dim3(IntShape<W>::THREADS), 0, s, g,
+                           (const cx<T>*)d.vbuf, partI, partR);
         GS_HIP_TRY(hipGetLastError());
     }
     if constexpr (NB > 0) {
         ProfScope _p(K_BND2D, s);
-        hipLaunchKernelGGL((adj_boundary_kernel<T, W, DEG, NB>), dim3(nt), dim3(BND_THREADS), 0, s, g, u, flags,
-                           partC, partX);
+        hipLaunchKernelGGL((adj_boundary_kernel<T, W, DEG, NB>), dim3(nt), dim3(BND_THREADS), 0, s, g,
+                           (const cx<T>*)d.vbuf, partC, partX);
         GS_HIP_TRY(hipGetLastError());
     }
     {
