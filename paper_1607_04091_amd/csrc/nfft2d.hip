@@ -83,16 +83,15 @@ constexpr int TILE_RB = 8;      // cell rows per column-owner block
 
 // ------------------------------------------------------------------ forward
 
-template <class T, int W, int DEG, int NB>
+// Interior interpolation of one tile's points (plus the boundary part, when
+// present, computed beforehand in sorted order), scales, weights and the
+// scatter to caller order.
+template <class T, int W, int DEG, bool BND>
 __global__ void __launch_bounds__(256) interp_tile_kernel(TileGeo<T> g, const cx<T>* __restrict__ grid,
-                                                          const cx<T>* __restrict__ sr, const cx<T>* __restrict__ sc,
-                                                          const cx<T>* __restrict__ X, cx<T>* __restrict__ y,
+                                                          const cx<T>* __restrict__ ybnd, cx<T>* __restrict__ y,
                                                           int flags) {
-    constexpr int TS = TILE_TS, PW = TS + W - 1, NCH = 2 * NB;
+    constexpr int TS = TILE_TS, PW = TS + W - 1;
     __shared__ cx<T> sG[PW * PW];
-    __shared__ cx<T> sSR[NCH > 0 ? NCH * PW : 1];
-    __shared__ cx<T> sSC[NCH > 0 ? NCH * PW : 1];
-    __shared__ cx<T> sXC[NCH > 0 ? NCH * NCH : 1];
     const int tile = blockIdx.x;
     const int q0 = g.cs[tile << (2 * g.lts)];
     const int q1 = g.cs[(tile + 1) << (2 * g.lts)];
@@ -103,19 +102,9 @@ __global__ void __launch_bounds__(256) interp_tile_kernel(TileGeo<T> g, const cx
         const int i = e / PW, j = e - i * PW;
         sG[e] = grid[(size_t)((ox + i) & g.mask) * g.ng + ((oy + j) & g.mask)];
     }
-    if constexpr (NB > 0) {
-        for (int e = threadIdx.x; e < NCH * PW; e += blockDim.x) {
-            const int r = e / PW, j = e - r * PW;
-            sSR[e] = sr[(size_t)r * g.ng + ((oy + j) & g.mask)];
-            sSC[e] = sc[(size_t)r * g.ng + ((ox + j) & g.mask)];
-        }
-        for (int e = threadIdx.x; e < NCH * NCH; e += blockDim.x) {
-            const int r = e / NCH, c = e - r * NCH;
-            sXC[e] = X[(size_t)g.bcol(r) * g.N + g.bcol(c)];
-        }
-    }
     __syncthreads();
     const size_t M = g.M;
+    const int nb = g.nb;
     for (int q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
         int cxg, cyg;
         T tx, ty;
@@ -134,30 +123,86 @@ __global__ void __launch_bounds__(256) interp_tile_kernel(TileGeo<T> g, const cx
             for (int b = 0; b < W; ++b) acc = cfma(acc, row[b], wy[b]);
             I = cfma(I, acc, wx[a]);
         }
-        const cx<T> Dx = g.chx[NB * M + q], Dy = g.chy[NB * M + q];
-        cx<T> res = cmul(cmul(Dx, Dy), I);
-        if constexpr (NB > 0) {
-            cx<T> ay[NCH];
-#pragma unroll
-            for (int r = 0; r < NCH; ++r) ay[r] = g.chy[(size_t)(r < NB ? r : r + 1) * M + q];
-#pragma unroll
-            for (int r = 0; r < NCH; ++r) {
-                const cx<T> ax = g.chx[(size_t)(r < NB ? r : r + 1) * M + q];
-                cx<T> S = czero<T>();
-#pragma unroll
-                for (int b = 0; b < W; ++b) S = cfma(S, sSR[r * PW + ly + b], wy[b]);
-                cx<T> cr = czero<T>();
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) cr = cmac(cr, ay[c], sXC[r * NCH + c]);
-                res = cmac(res, ax, cadd(cmul(Dy, S), cr));
-                cx<T> Cc = czero<T>();
-#pragma unroll
-                for (int a = 0; a < W; ++a) Cc = cfma(Cc, sSC[r * PW + lx + a], wx[a]);
-                res = cmac(res, cmul(ay[r], Dx), Cc);
-            }
-        }
+        cx<T> res = cmul(cmul(g.chx[nb * M + q], g.chy[nb * M + q]), I);
+        if constexpr (BND) res = cadd(res, ybnd[q]);
         if (flags & GS_WEIGHTED) res = cscale(res, g.smu[q]);
         y[(flags & GS_SORTED) ? q : g.perm[q]] = res;
+    }
+}
+
+// Boundary part of T x for one tile's points (App. C): with ax_r, ay_c the
+// boundary channels of the point and Dx, Dy its interior scales,
+//   ybnd = Dy sum_r ax_r S_r + Dx sum_c ay_c C_c + sum_r ax_r sum_c X[r][c] ay_c,
+// S_r the 1D interpolation (along y) of the row-side grid r and C_c that of the
+// column-side grid c (along x).  Written in sorted order; the interior kernel adds it.
+template <class T, int W, int DEG, int NB>
+__global__ void __launch_bounds__(256) interp_bnd_kernel(TileGeo<T> g, const cx<T>* __restrict__ sr,
+                                                         const cx<T>* __restrict__ sc, const cx<T>* __restrict__ X,
+                                                         cx<T>* __restrict__ ybnd) {
+    constexpr int TS = TILE_TS, PW = TS + W - 1, NCH = 2 * NB;
+    __shared__ cx<T> sSR[NCH * PW];
+    __shared__ cx<T> sSC[NCH * PW];
+    __shared__ cx<T> sXC[NCH * NCH];
+    const int tile = blockIdx.x;
+    const int q0 = g.cs[tile << (2 * g.lts)];
+    const int q1 = g.cs[(tile + 1) << (2 * g.lts)];
+    if (q0 == q1) return;
+    const int t0x = (tile / g.ntx) << g.lts, t0y = (tile % g.ntx) << g.lts;
+    const int ox = t0x - (W / 2 - 1), oy = t0y - (W / 2 - 1);
+    for (int e = threadIdx.x; e < NCH * PW; e += blockDim.x) {
+        const int r = e / PW, j = e - r * PW;
+        sSR[e] = sr[(size_t)r * g.ng + ((oy + j) & g.mask)];
+        sSC[e] = sc[(size_t)r * g.ng + ((ox + j) & g.mask)];
+    }
+    for (int e = threadIdx.x; e < NCH * NCH; e += blockDim.x) {
+        const int r = e / NCH, c = e - r * NCH;
+        sXC[e] = X[(size_t)g.bcol(r) * g.N + g.bcol(c)];
+    }
+    __syncthreads();
+    const size_t M = g.M;
+    for (int q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+        int cxg, cyg;
+        T tx, ty;
+        decode_pos2(g.pos[q], g.G, cxg, tx);
+        decode_pos2(g.pos[M + q], g.G, cyg, ty);
+        const int lx = cxg - t0x, ly = cyg - t0y;
+        T w[W];
+        // row sides: sum_r ax_r S_r
+        taps_all<T, W, DEG>(ty, g.win, w);
+        cx<T> sR = czero<T>();
+#pragma unroll 2
+        for (int r = 0; r < NCH; ++r) {
+            const cx<T>* s = sSR + r * PW + ly;
+            cx<T> S = czero<T>();
+#pragma unroll
+            for (int b = 0; b < W; ++b) S = cfma(S, s[b], w[b]);
+            sR = cmac(sR, g.chx[(size_t)(r < NB ? r : r + 1) * M + q], S);
+        }
+        cx<T> res = cmul(g.chy[NB * M + q], sR);
+        // column sides: sum_c ay_c C_c
+        taps_all<T, W, DEG>(tx, g.win, w);
+        cx<T> sC = czero<T>();
+#pragma unroll 2
+        for (int c = 0; c < NCH; ++c) {
+            const cx<T>* s = sSC + c * PW + lx;
+            cx<T> C = czero<T>();
+#pragma unroll
+            for (int a = 0; a < W; ++a) C = cfma(C, s[a], w[a]);
+            sC = cmac(sC, g.chy[(size_t)(c < NB ? c : c + 1) * M + q], C);
+        }
+        res = cmac(res, g.chx[NB * M + q], sC);
+        // corners: sum_r ax_r sum_c X[r][c] ay_c
+        cx<T> ay[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) ay[c] = g.chy[(size_t)(c < NB ? c : c + 1) * M + q];
+#pragma unroll 2
+        for (int r = 0; r < NCH; ++r) {
+            cx<T> t = czero<T>();
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) t = cmac(t, sXC[r * NCH + c], ay[c]);
+            res = cmac(res, g.chx[(size_t)(r < NB ? r : r + 1) * M + q], t);
+        }
+        ybnd[q] = res;
     }
 }
 
@@ -712,10 +757,17 @@ template <class T, int NB>
 hipError_t interp2d_tile_nb(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hipStream_t s) {
     const PrecData<T>& d = prec<T>(P);
     const TileGeo<T> g = make_tile_geo<T>(P);
+    constexpr int W = TileWin<T>::W, DEG = TileWin<T>::DEG;
     const int nt = g.ntx * g.ntx;
+    if constexpr (NB > 0) {
+        ProfScope _p(K_INTERP_BND, s);
+        hipLaunchKernelGGL((interp_bnd_kernel<T, W, DEG, NB>), dim3(nt), dim3(256), 0, s, g, (const cx<T>*)d.sr,
+                           (const cx<T>*)d.sc, x, d.ybuf);
+        GS_HIP_TRY(hipGetLastError());
+    }
     ProfScope _p(K_INTERP2D, s);
-    hipLaunchKernelGGL((interp_tile_kernel<T, TileWin<T>::W, TileWin<T>::DEG, NB>), dim3(nt), dim3(256), 0, s, g,
-                       d.grid, d.sr, d.sc, x, y, flags);
+    hipLaunchKernelGGL((interp_tile_kernel<T, W, DEG, (NB > 0)>), dim3(nt), dim3(256), 0, s, g, (const cx<T>*)d.grid,
+                       (const cx<T>*)d.ybuf, y, flags);
     return hipGetLastError();
 }
 
