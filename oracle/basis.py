@@ -74,6 +74,25 @@ def columns_1d(xi, J: int, p: int) -> np.ndarray:
     return B
 
 
+def column_1d(xi, J: int, p: int, n: int) -> np.ndarray:
+    """b_n(xi_m) for a single column n: the formulas of columns_1d for that
+    column only (Sec. 4), so that one coefficient of T^H u can be formed over
+    many points without building every column."""
+    check_scale(J, p)
+    xi = np.asarray(xi, dtype=np.float64)
+    N = 1 << J
+    if not 0 <= n < N:
+        raise ValueError("column index out of range")
+    eta = xi / N
+    scale = 2.0 ** (-J / 2.0)
+    nb = n_boundary(p)
+    if nb <= n < N - nb:
+        return scale * unit_phase([n - N // 2], eta, -1.0)[0] * db.phi_hat(eta, p)
+    if n < nb:
+        return scale * half_turn_phase(xi, +1.0) * cdv.left_phi_hat(eta, p)[n]
+    return scale * half_turn_phase(xi, -1.0) * cdv.right_phi_hat(eta, p)[N - 1 - n]
+
+
 def dense_T_1d(xi, J: int, p: int) -> np.ndarray:
     """T of shape (M, N), 1D."""
     return columns_1d(xi, J, p).T.copy()

@@ -258,6 +258,10 @@ int gs_plan(gs_plan_t** out, int dim, int J, int p, int64_t M, const double* xi,
     }
     P.n1 = 1 << P.lg1; P.n2 = 1 << P.lg2;
     P.ts = std::min(gs::TILE, P.ng);
+    if (dim == 2 && P.ts == gs::TILE) {
+        P.cr1 = gs::colfft_r1(P.ng);
+        P.cr2 = P.cr1 ? P.ng / P.cr1 : 0;
+    }
     hipStream_t s = (hipStream_t)stream;
 
     // ---- host math (FP64 / extended)

@@ -79,6 +79,8 @@ struct Plan {
     int ng = 0, G = 0;              // grid size per dim and log2
     int ts = 0;                     // 2D tile side in cells (min(TILE, ng))
     int n1 = 0, n2 = 0, lg1 = 0, lg2 = 0;   // four-step split (1D, ng > FFT_MAX_LDS)
+    int cr1 = 0, cr2 = 0;           // 2D column transform split ng = cr1 * cr2 (0: natural row order);
+                                    // frequency row k of the grid is stored in row cr2 * (k % cr1) + k / cr1
     int32_t* perm = nullptr;        // [M] internal -> caller index
     int32_t* cell_start = nullptr;  // [ng^dim + 1] points sorted by cell (row-major)
     PrecData<double> d64;
@@ -109,6 +111,10 @@ template <> inline const PrecData<float>& prec<float>(const Plan& p) { return p.
 // launch helpers (defined in nfft.hip / fft.hip)
 template <class T> hipError_t launch_apply_T(const Plan& P, const C_t<T>* x, C_t<T>* y, int flags, hipStream_t s);
 template <class T> hipError_t launch_apply_TH(const Plan& P, const C_t<T>* u, C_t<T>* x, int flags, hipStream_t s);
+
+// column split of a 2D grid of side ng for the register column transform
+// (0: single-pass LDS transform, natural row order)
+inline int colfft_r1(int ng) { return ng == 1024 || ng == 512 ? 32 : (ng == 256 ? 16 : 0); }
 
 inline int ilog2(int64_t v) { int l = 0; while ((int64_t(1) << l) < v) ++l; return l; }
 

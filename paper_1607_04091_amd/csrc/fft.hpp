@@ -101,6 +101,122 @@ inline hipError_t launch_fft(const Op& op, int ntrans, int n, int CB, const cx<T
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ register FFTs
+// Column transforms of an ng x ng grid with ng = R1 * R2, two passes over HBM.
+// A thread holds one R-point transform in registers; a wavefront covers 64
+// adjacent columns, so every load and store is a contiguous row segment.
+//   pass 1, thread (col, n2): Y[k1] = W_ng^(n2 k1) sum_n1 x[R2 n1 + n2] W_R1^(n1 k1),
+//     written back to row R2 k1 + n2;
+//   pass 2, thread (col, k1): X[k1 + R1 k2] = sum_n2 Y[R2 k1 + n2] W_R2^(n2 k2),
+//     written to row R2 k1 + k2.
+// Both passes are in place; frequency row k ends in row R2 (k mod R1) + k / R1.
+template <int R>
+__host__ __device__ constexpr int brev_ct(int i) {
+    int r = 0;
+    for (int b = 1; b < R; b <<= 1) {
+        r = (r << 1) | (i & 1);
+        i >>= 1;
+    }
+    return r;
+}
+
+// in-register R-point DFT, natural order in and out; tw[m * tstep] = e^{-2 pi i m / R}
+template <class T, int R, int DIR>
+__device__ inline void reg_fft(cx<T>* v, const cx<T>* tw, int tstep) {
+    cx<T> a[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) a[i] = v[brev_ct<R>(i)];
+#pragma unroll
+    for (int h = 1; h < R; h <<= 1) {
+#pragma unroll
+        for (int k = 0; k < h; ++k) {
+            cx<T> w = tw[k * (R / (2 * h)) * tstep];
+            if (DIR > 0) w.y = -w.y;
+#pragma unroll
+            for (int g = 0; g < R; g += 2 * h) {
+                const cx<T> u = a[g + k];
+                const cx<T> t = k == 0 ? a[g + k + h] : cmul(a[g + k + h], w);
+                a[g + k] = cadd(u, t);
+                a[g + k + h] = csub(u, t);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = a[i];
+}
+
+// rows whose frequency lies in [-(N/2) + nb, N/2 - nb): the interior of the 2D grid
+__device__ inline bool grid_row_active(int q, int ng, int N, int nb) {
+    const int k = q < (ng >> 1) ? q : q - ng;
+    return k >= -(N >> 1) + nb && k < (N >> 1) - nb;
+}
+
+// prune_in: inactive input rows are zero (forward); prune_out: inactive output rows are not stored (adjoint)
+template <class T, int R1, int R2, int DIR>
+__global__ void __launch_bounds__(256) colfft_pass1(cx<T>* __restrict__ grid, const cx<T>* __restrict__ tw, int N,
+                                                    int nb, int prune_in) {
+    constexpr int L = R1 * R2;
+    __shared__ cx<T> stw[L];
+    for (int e = threadIdx.x; e < L; e += 256) stw[e] = tw[e];
+    __syncthreads();
+    const int col = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int n2 = blockIdx.y * 4 + (threadIdx.x >> 6);
+    cx<T> v[R1];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) {
+        const int q = R2 * n1 + n2;
+        v[n1] = (prune_in && !grid_row_active(q, L, N, nb)) ? czero<T>() : grid[(size_t)q * L + col];
+    }
+    reg_fft<T, R1, DIR>(v, stw, L / R1);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+        cx<T> w = stw[(n2 * k1) & (L - 1)];
+        if (DIR > 0) w.y = -w.y;
+        grid[(size_t)(R2 * k1 + n2) * L + col] = cmul(v[k1], w);
+    }
+}
+
+template <class T, int R1, int R2, int DIR>
+__global__ void __launch_bounds__(256) colfft_pass2(cx<T>* __restrict__ grid, const cx<T>* __restrict__ tw, int N,
+                                                    int nb, int prune_out) {
+    constexpr int L = R1 * R2;
+    __shared__ cx<T> stw[L];
+    for (int e = threadIdx.x; e < L; e += 256) stw[e] = tw[e];
+    __syncthreads();
+    const int col = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int k1 = blockIdx.y * 4 + (threadIdx.x >> 6);
+    cx<T> v[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) v[n2] = grid[(size_t)(R2 * k1 + n2) * L + col];
+    reg_fft<T, R2, DIR>(v, stw, L / R2);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) {
+        if (prune_out && !grid_row_active(k1 + R1 * k2, L, N, nb)) continue;
+        grid[(size_t)(R2 * k1 + k2) * L + col] = v[k2];
+    }
+}
+
+template <class T, int R1, int R2, int DIR>
+inline hipError_t launch_colfft(cx<T>* grid, const cx<T>* tw, int N, int nb, int prune_in, int prune_out,
+                                hipStream_t s) {
+    constexpr int L = R1 * R2;
+    hipLaunchKernelGGL((colfft_pass1<T, R1, R2, DIR>), dim3(L / 64, R2 / 4), dim3(256), 0, s, grid, tw, N, nb,
+                       prune_in);
+    GS_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL((colfft_pass2<T, R1, R2, DIR>), dim3(L / 64, R1 / 4), dim3(256), 0, s, grid, tw, N, nb,
+                       prune_out);
+    return hipGetLastError();
+}
+
+template <class T, int DIR>
+inline hipError_t launch_colfft_split(int cr1, int ng, cx<T>* grid, const cx<T>* tw, int N, int nb, int prune_in,
+                                      int prune_out, hipStream_t s) {
+    if (ng == 1024 && cr1 == 32) return launch_colfft<T, 32, 32, DIR>(grid, tw, N, nb, prune_in, prune_out, s);
+    if (ng == 512 && cr1 == 32) return launch_colfft<T, 32, 16, DIR>(grid, tw, N, nb, prune_in, prune_out, s);
+    if (ng == 256 && cr1 == 16) return launch_colfft<T, 16, 16, DIR>(grid, tw, N, nb, prune_in, prune_out, s);
+    return hipErrorInvalidValue;
+}
+
 // columns per workgroup for strided (column) passes: keep LDS <= 32 KB
 template <class T>
 inline int col_batch(int n) {

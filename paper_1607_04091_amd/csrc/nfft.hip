@@ -137,8 +137,10 @@ template <class T> struct OpT2SideCols {
 
 template <class T> struct OpTH2Rows {
     const cx<T>* grid; const cx<T>* sr; cx<T>* X; const T* deap; int N, nb, ng;
+    int cr1 = 0, cr2 = 0;   // storage order of the grid rows (see Plan::cr1)
+    __device__ int row(int k) const { return cr1 ? cr2 * (k & (cr1 - 1)) + k / cr1 : k; }
     __device__ cx<T> load(int i, int q) const {
-        if (i >= nb && i < N - nb) return grid[(size_t)((i - (N >> 1)) & (ng - 1)) * ng + q];
+        if (i >= nb && i < N - nb) return grid[(size_t)row((i - (N >> 1)) & (ng - 1)) * ng + q];
         return sr[(size_t)(i < nb ? i : nb + (N - 1 - i)) * ng + q];
     }
     __device__ void store(int i, int q, cx<T> v) const {
@@ -543,8 +545,11 @@ hipError_t launch_apply_T(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hi
     if (P.dim == 2) {
         GS_TIMED(K_FFT_ROWS_T, GS_HIP_TRY((launch_fft<T, -1>(OpT2Rows<T>{x, d.grid, d.sr, d.deap, N, nb, ng}, N, ng, 1,
                                                            d.tw, ng, s))));
-        GS_TIMED(K_FFT_COLS_T, GS_HIP_TRY((launch_fft<T, -1>(OpCols<T>{d.grid, N, nb, ng, 1}, ng, ng,
-                                                           col_batch<T>(ng), d.tw, ng, s))));
+        if (P.cr1)
+            GS_TIMED(K_FFT_COLS_T, GS_HIP_TRY((launch_colfft_split<T, -1>(P.cr1, ng, d.grid, d.tw, N, nb, 1, 0, s))));
+        else
+            GS_TIMED(K_FFT_COLS_T, GS_HIP_TRY((launch_fft<T, -1>(OpCols<T>{d.grid, N, nb, ng, 1}, ng, ng,
+                                                               col_batch<T>(ng), d.tw, ng, s))));
         if (nb)
             GS_TIMED(K_FFT_SIDECOLS_T,
                      GS_HIP_TRY((launch_fft<T, -1>(OpT2SideCols<T>{x, d.sc, d.deap, N, nb, ng}, 2 * nb, ng,
@@ -572,10 +577,14 @@ hipError_t launch_apply_TH(const Plan& P, const cx<T>* u, cx<T>* x, int flags, h
     const int N = P.N, nb = P.nb, ng = P.ng;
     if (P.dim == 2 && P.ts == TILE) {
         GS_HIP_TRY(adjoint2d_tile<T>(P, u, x, flags, s));
-        GS_TIMED(K_FFT_COLS_TH, GS_HIP_TRY((launch_fft<T, +1>(OpCols<T>{d.grid, N, nb, ng, 0}, ng, ng,
-                                                            col_batch<T>(ng), d.tw, ng, s))));
-        GS_TIMED(K_FFT_ROWS_TH, GS_HIP_TRY((launch_fft<T, +1>(OpTH2Rows<T>{d.grid, d.sr, x, d.deap, N, nb, ng}, N, ng,
-                                                            1, d.tw, ng, s))));
+        if (P.cr1)
+            GS_TIMED(K_FFT_COLS_TH, GS_HIP_TRY((launch_colfft_split<T, +1>(P.cr1, ng, d.grid, d.tw, N, nb, 0, 1, s))));
+        else
+            GS_TIMED(K_FFT_COLS_TH, GS_HIP_TRY((launch_fft<T, +1>(OpCols<T>{d.grid, N, nb, ng, 0}, ng, ng,
+                                                                col_batch<T>(ng), d.tw, ng, s))));
+        GS_TIMED(K_FFT_ROWS_TH,
+                 GS_HIP_TRY((launch_fft<T, +1>(OpTH2Rows<T>{d.grid, d.sr, x, d.deap, N, nb, ng, P.cr1, P.cr2}, N, ng,
+                                               1, d.tw, ng, s))));
         if (nb)
             GS_TIMED(K_FFT_SIDECOLS_TH,
                      GS_HIP_TRY((launch_fft<T, +1>(OpTH2SideCols<T>{d.sc, x, d.deap, N, nb, ng}, 2 * nb, ng,

@@ -33,6 +33,7 @@ namespace gs {
 template <class T>
 struct TileGeo {
     int N, nb, ng, G, mask, M, ts, lts, ntx;
+    int cr1, cr2;       // storage order of the transformed grid rows (see Plan::cr1)
     const P_t<T>* pos;
     const cx<T>* chx;
     const cx<T>* chy;
@@ -40,6 +41,7 @@ struct TileGeo {
     const T* win;
     const int32_t* perm;
     const int32_t* cs;
+    __device__ int grow(int k) const { return cr1 ? cr2 * (k & (cr1 - 1)) + k / cr1 : k; }
     __device__ int bcol(int r) const { return r < nb ? r : N - 1 - (r - nb); }
     __device__ int bchan(int r) const { return r < nb ? r : r + 1; }
 };
@@ -100,7 +102,7 @@ __global__ void __launch_bounds__(256) interp_tile_kernel(TileGeo<T> g, const cx
     const int ox = t0x - (W / 2 - 1), oy = t0y - (W / 2 - 1);
     for (int e = threadIdx.x; e < PW * PW; e += blockDim.x) {
         const int i = e / PW, j = e - i * PW;
-        sG[e] = grid[(size_t)((ox + i) & g.mask) * g.ng + ((oy + j) & g.mask)];
+        sG[e] = grid[(size_t)g.grow((ox + i) & g.mask) * g.ng + ((oy + j) & g.mask)];
     }
     __syncthreads();
     const size_t M = g.M;
@@ -688,52 +690,66 @@ __global__ void merge_grid_kernel(TileGeo<T> g, const cx<T>* __restrict__ partI,
     grid[idx] = s;
 }
 
-// side grids: sr[r][gy] sums over every tile row tx, sc[c][gx] over every tile column ty
+// Side grids and corners from the tile partials, in a fixed order.
+//   blocks [0, nside): 32 positions gl of one side grid (row sides sr[r][gy]: the
+//     tiles of tile column gy; column sides sc[c][gx]: the tiles of tile row gx),
+//     8 thread groups each summing a fixed run of tiles, then the 8 group sums in order;
+//   blocks [nside, nside + nch^2): one corner entry X[bcol(r)][bcol(c)] over all tiles.
+constexpr int MERGE_GROUPS = 8;
 template <class T, int W>
-__global__ void merge_sides_kernel(TileGeo<T> g, const cx<T>* __restrict__ partR, const cx<T>* __restrict__ partC,
-                                   cx<T>* __restrict__ sr, cx<T>* __restrict__ sc) {
+__global__ void __launch_bounds__(256) merge_sides_kernel(TileGeo<T> g, const cx<T>* __restrict__ partR,
+                                                          const cx<T>* __restrict__ partC,
+                                                          const cx<T>* __restrict__ partX, int nside,
+                                                          cx<T>* __restrict__ sr, cx<T>* __restrict__ sc,
+                                                          cx<T>* __restrict__ X) {
     constexpr int TS = TILE_TS, PW = TS + W - 1, H = W / 2 - 1;
+    __shared__ cx<T> sh[256];
     const int nch = 2 * g.nb;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= 2 * nch * g.ng) return;
-    const int which = idx / (nch * g.ng);
-    const int r = (idx / g.ng) % nch, gl = idx % g.ng;
+    const int tid = threadIdx.x;
+    if ((int)blockIdx.x >= nside) {
+        const int e = blockIdx.x - nside;   // (r, c)
+        const int nt = g.ntx * g.ntx;
+        cx<T> s = czero<T>();
+        for (int t = tid; t < nt; t += 256) s = cadd(s, partX[(size_t)t * nch * nch + e]);
+        sh[tid] = s;
+        __syncthreads();
+        for (int k = 128; k > 0; k >>= 1) {
+            if (tid < k) sh[tid] = cadd(sh[tid], sh[tid + k]);
+            __syncthreads();
+        }
+        if (tid == 0) X[(size_t)g.bcol(e / nch) * g.N + g.bcol(e % nch)] = sh[0];
+        return;
+    }
+    const int per = g.ng / 32;                      // blocks per side grid
+    const int which = blockIdx.x / (nch * per);
+    const int r = (blockIdx.x / per) % nch;
+    const int gl = (blockIdx.x % per) * 32 + (tid & 31);
+    const int grp = tid >> 5;
     const int sl = (gl + H) & g.mask;
     const int t0 = sl >> g.lts, p0 = sl & (TS - 1);
     const bool o = p0 < W - 1;
     const int tm = (t0 + g.ntx - 1) % g.ntx;
+    const int tpg = (g.ntx + MERGE_GROUPS - 1) / MERGE_GROUPS;
+    const int ta = grp * tpg, tb = min(g.ntx, ta + tpg);
     cx<T> s = czero<T>();
-    if (which == 0) {   // row sides: tiles (t, t0) and (t, tm) for all t
-        for (int t = 0; t < g.ntx; ++t) {
+    if (which == 0) {   // row sides: tiles (t, t0) and (t, tm)
+        for (int t = ta; t < tb; ++t) {
             if (o) s = cadd(s, partR[((size_t)(t * g.ntx + tm) * nch + r) * PW + p0 + TS]);
             s = cadd(s, partR[((size_t)(t * g.ntx + t0) * nch + r) * PW + p0]);
         }
-        sr[(size_t)r * g.ng + gl] = s;
     } else {            // column sides: tiles (t0, t) and (tm, t)
-        for (int t = 0; t < g.ntx; ++t) {
+        for (int t = ta; t < tb; ++t) {
             if (o) s = cadd(s, partC[((size_t)(tm * g.ntx + t) * nch + r) * PW + p0 + TS]);
             s = cadd(s, partC[((size_t)(t0 * g.ntx + t) * nch + r) * PW + p0]);
         }
-        sc[(size_t)r * g.ng + gl] = s;
     }
-}
-
-// corners: X[bcol(r)][bcol(c)] = sum over all tiles (fixed tree order)
-template <class T>
-__global__ void __launch_bounds__(256) merge_corners_kernel(TileGeo<T> g, const cx<T>* __restrict__ partX, int ntiles,
-                                                            cx<T>* __restrict__ X) {
-    __shared__ cx<T> sh[256];
-    const int nch = 2 * g.nb;
-    const int e = blockIdx.x;       // (r, c)
-    cx<T> s = czero<T>();
-    for (int t = threadIdx.x; t < ntiles; t += 256) s = cadd(s, partX[(size_t)t * nch * nch + e]);
-    sh[threadIdx.x] = s;
+    sh[tid] = s;
     __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) sh[threadIdx.x] = cadd(sh[threadIdx.x], sh[threadIdx.x + k]);
-        __syncthreads();
+    if (grp == 0) {
+#pragma unroll
+        for (int k = 1; k < MERGE_GROUPS; ++k) s = cadd(s, sh[k * 32 + tid]);
+        (which == 0 ? sr : sc)[(size_t)r * g.ng + gl] = s;
     }
-    if (threadIdx.x == 0) X[(size_t)g.bcol(e / nch) * g.N + g.bcol(e % nch)] = sh[0];
 }
 
 // ------------------------------------------------------------------ launchers
@@ -744,6 +760,7 @@ TileGeo<T> make_tile_geo(const Plan& P) {
     TileGeo<T> g;
     g.N = P.N; g.nb = P.nb; g.ng = P.ng; g.G = P.G; g.mask = P.ng - 1; g.M = (int)P.M;
     g.ts = P.ts; g.lts = ilog2(P.ts); g.ntx = P.ng / P.ts;
+    g.cr1 = P.cr1; g.cr2 = P.cr2;
     g.pos = d.pos; g.chx = d.chx; g.chy = d.chy; g.smu = d.smu; g.win = d.win;
     g.perm = P.perm; g.cs = P.cell_start;
     return g;
@@ -806,10 +823,9 @@ hipError_t adjoint2d_tile_nb(const Plan& P, const cx<T>* u, cx<T>* x, int flags,
                            d.grid);
         GS_HIP_TRY(hipGetLastError());
         if (NB > 0) {
-            hipLaunchKernelGGL((merge_sides_kernel<T, W>), dim3((2 * nch * g.ng + 255) / 256), dim3(256), 0, s, g,
-                               partR, partC, d.sr, d.sc);
-            GS_HIP_TRY(hipGetLastError());
-            hipLaunchKernelGGL((merge_corners_kernel<T>), dim3(nch * nch), dim3(256), 0, s, g, partX, nt, x);
+            const int nside = 2 * nch * (g.ng / 32);
+            hipLaunchKernelGGL((merge_sides_kernel<T, W>), dim3(nside + nch * nch), dim3(256), 0, s, g, partR, partC,
+                               partX, nside, d.sr, d.sc, x);
             GS_HIP_TRY(hipGetLastError());
         }
     }

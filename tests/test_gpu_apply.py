@@ -100,6 +100,8 @@ TWO_D = [
     (6, 3, "jitter", 9000),
     (3, 4, "random", 400),        # no interior
     (6, 4, "random", 5000),
+    (7, 4, "random", 6000),       # 256^2 grid: two-pass register column transform (16 x 16)
+    (8, 3, "spiral", 8000),       # 512^2 grid (32 x 16)
 ]
 
 

@@ -269,6 +269,15 @@ def test_selected_outputs_match_full_products():
     assert np.allclose(basis.coeffs_TH_2d(xi2, J, p, u, ij), Z[ij[:, 0], ij[:, 1]], atol=1e-13)
 
 
+@pytest.mark.parametrize("p", [1, 2, 4])
+def test_single_column_matches_all_columns(p):
+    J = 5
+    xi = np.random.default_rng(4).uniform(-40, 40, 500)
+    B = basis.columns_1d(xi, J, p)
+    for n in (0, 1, p - 1, p, 16, 31 - p, 31 - p + 1, 31):
+        assert np.array_equal(basis.column_1d(xi, J, p, n), B[n])
+
+
 # ------------------------------------------------------------------ NDFT (O5)
 
 def test_ndft_uniform_reduces_to_dft():
