@@ -35,33 +35,43 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Algorithmic bytes per launch of each kernel (measurement
-# section): the bytes the method itself must move, c = bytes per complex,
-# r = bytes per real, pos = bytes per fixed-point coordinate.
-def algorithmic_bytes(name, M, N, ng, nb, c, r, pos):
-    nch = 2 * nb + 1
+# Algorithmic bytes per launch of each kernel of the 2D tile path: every array
+# the kernel must touch, read or written once (c = bytes per complex, r = bytes
+# per real, pos = bytes per fixed-point coordinate).  nch = 2p boundary
+# channels per dimension; tiles of 32 x 32 cells padded by W - 1.
+def algorithmic_bytes(name, M, N, ng, nb, c, r, pos, W=8, TS=32):
+    nbc = 2 * nb
+    nt = (ng // TS) ** 2
+    pw = TS + W - 1
     grid = ng * ng * c
-    side = 4 * nb * ng * c
-    if name == "interp2d":
-        # coordinates, sqrt(mu), both channel sets, permutation, y; grid + side grids once
-        return M * (2 * pos + r + 2 * nch * c + 4 + c) + grid + side
-    if name == "spread2d":
-        return M * (2 * pos + c) + grid + 4 * (ng * ng + 1)
-    if name == "side_rows_partial":
-        return M * (pos + c + (nb * 2 + 1) * c) + 4 * (ng * ng + 1)
-    if name == "side_cols_partial":
-        return M * (pos + c + (nb * 2 + 1) * c) + 4 * (ng * ng + 1)
-    if name == "adj_prep":
-        return M * (4 + c + r + 2 * c + c + c)
-    if name == "boundary_partial":
-        return M * (4 * nb * c + c)
-    if name in ("fft_rows_T",):
-        return N * N * c + (N // 2 * 2) * ng * c + 2 * nb * ng * c
-    if name in ("fft_cols_T", "fft_cols_TH"):
-        return (N + ng) * ng * c
-    if name in ("fft_rows_TH",):
+    if name == "interp_bnd2d":      # coords, D_x, D_y, both boundary channel sets, boundary part out; side grids
+        return M * (2 * pos + 2 * (nbc + 1) * c + c) + 2 * nbc * ng * c + nbc * nbc * c
+    if name == "interp2d":          # coords, D_x, D_y, boundary part, sqrt(mu), perm, y out; grid once
+        return M * (2 * pos + 2 * c + c + r + 4 + c) + grid
+    if name == "adj_prep":          # u gathered through perm, sqrt(mu), sorted scaled input out
+        return M * (c + 4 + r + c)
+    if name == "spread2d":          # coords, scaled input, D_x, D_y, x-boundary channels; tile partials out
+        return M * (2 * pos + c + 2 * c + nbc * c) + nt * (pw * pw + nbc * pw) * c
+    if name == "boundary2d":        # x coordinate, scaled input, D_x, both boundary channel sets; partials out
+        return M * (pos + c + c + 2 * nbc * c) + nt * (nbc * pw + nbc * nbc) * c
+    if name == "merge_tiles":       # tile partials in; grid, side grids and corners out
+        return nt * (pw * pw + 2 * nbc * pw + nbc * nbc) * c + grid + 2 * nbc * ng * c + nbc * nbc * c
+    if name in ("fft_cols_T", "fft_cols_TH"):   # two passes, each reads and writes the grid
+        return 4 * grid
+    if name == "fft_rows_T":        # coefficients in, N transformed rows (interior and row sides) out
+        return N * N * c + N * ng * c
+    if name == "fft_rows_TH":
         return N * ng * c + N * N * c
+    if name in ("fft_sidecols_T", "fft_sidecols_TH"):
+        return 2 * nbc * ng * c
     return None
+
+
+# Algorithmic bytes of one weighted apply pair (the method's stored-block
+# formulation): per point coords, sqrt(mu), per-dimension scales, the 2dp
+# boundary values and the in/out value; grid and FFT traffic ~ 13 N^2 c.
+def pair_bytes(M, N, p, c, r, d=2):
+    return 2 * (M * ((d + 1) * r + (d + 1 + 2 * d * p) * c) + 13 * N * N * c)
 
 
 def oracle_baseline(pts, mu, J, p, sample, M):
@@ -176,17 +186,25 @@ def main():
     prof = gs.gs_profile_read()
     gs.gs_profile_enable(False)
     kernels = {k: {"launches": n, "avg_us": 1000.0 * t / n} for k, (n, t) in prof.items()}
-    for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["avg_us"] * kv[1]["launches"]):
-        log(f"[bench]   {k:20s} {v['launches']:5d} launches  avg {v['avg_us']:9.2f} us")
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"] / nprof)
-    nb = p
-    ab = algorithmic_bytes(dom, M, N, 2 * N, nb, 8, 4, 4)
+    for k, v in kernels.items():
+        ab = algorithmic_bytes(k, M, N, 2 * N, p, 8, 4, 4)
+        if ab is not None:
+            v["gbs"] = ab / (v["avg_us"] * 1e-6) / 1e9
+    ab = algorithmic_bytes(dom, M, N, 2 * N, p, 8, 4, 4)
     roof = None
     if ab is not None:
         ach = ab / (kernels[dom]["avg_us"] * 1e-6) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                 "algorithmic_bytes_per_launch": int(ab), "avg_launch_us": round(kernels[dom]["avg_us"], 2)}
+    for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["avg_us"] * kv[1]["launches"]):
+        log(f"[bench]   {k:20s} {v['launches']:5d} launches  avg {v['avg_us']:9.2f} us"
+            + (f"  {v['gbs']:7.0f} GB/s algorithmic" if "gbs" in v else ""))
+    pb = pair_bytes(M, N, p, 8, 4)
+    pair_roof = {"algorithmic_bytes": int(pb), "achieved_gbs": round(pb / (ms32 * 1e-3) / 1e9, 1),
+                 "frac": round(pb / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "ceiling_pairs_per_s": round(HBM_PEAK_GBS * 1e9 / pb, 1)}
 
     solve = {}
     if not args.no_solve:
@@ -240,6 +258,7 @@ def main():
         "init_s": round(t_init, 3),
         "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()},
         "roofline": roof,
+        "pair_roofline": pair_roof,
         "solve": solve,
         "cpu_baseline": cpu,
     }

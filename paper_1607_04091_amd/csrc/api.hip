@@ -57,7 +57,7 @@ void free_prec(gs::PrecData<T>& d) {
 void free_plan(gs::Plan& P) {
     free_prec(P.d64);
     free_prec(P.d32);
-    dfree(P.perm); dfree(P.cell_start);
+    dfree(P.perm); dfree(P.cell_start); dfree(P.tile_order);
     dfree(P.smu64); dfree(P.b); dfree(P.r); dfree(P.q); dfree(P.ps); dfree(P.ss);
     dfree(P.q32); dfree(P.r32); dfree(P.p32); dfree(P.s32);
     dfree(P.red); dfree(P.scal); dfree(P.hist);
@@ -298,6 +298,16 @@ int gs_plan(gs_plan_t** out, int dim, int J, int p, int64_t M, const double* xi,
     H.cell_start.assign(ncells + 1, 0);
     for (int64_t m = 0; m < M; ++m) H.cell_start[key[m] + 1]++;
     for (int64_t c = 0; c < ncells; ++c) H.cell_start[c + 1] += H.cell_start[c];
+    // 2D tiles in decreasing point count: the tile kernels take the heaviest tiles first
+    std::vector<int32_t> tile_order;
+    if (dim == 2 && P.ts == gs::TILE) {
+        const int64_t nt = (int64_t)(P.ng / P.ts) * (P.ng / P.ts), tc = (int64_t)P.ts * P.ts;
+        tile_order.resize(nt);
+        for (int64_t t = 0; t < nt; ++t) tile_order[t] = (int32_t)t;
+        std::stable_sort(tile_order.begin(), tile_order.end(), [&](int32_t a, int32_t b) {
+            return H.cell_start[(a + 1) * tc] - H.cell_start[a * tc] > H.cell_start[(b + 1) * tc] - H.cell_start[b * tc];
+        });
+    }
     H.perm.resize(M);
     {
         std::vector<int32_t> fill(H.cell_start.begin(), H.cell_start.end() - 1);
@@ -324,6 +334,12 @@ int gs_plan(gs_plan_t** out, int dim, int J, int p, int64_t M, const double* xi,
         if ((e = hipMemcpy(P.cell_start, H.cell_start.data(), (ncells + 1) * sizeof(int32_t),
                            hipMemcpyHostToDevice)) != hipSuccess)
             break;
+        if (!tile_order.empty()) {
+            if ((e = dalloc(P, P.tile_order, tile_order.size())) != hipSuccess) break;
+            if ((e = hipMemcpy(P.tile_order, tile_order.data(), tile_order.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice)) != hipSuccess)
+                break;
+        }
         if (precision == GS_F64 || precision == GS_F32_MIXED)
             if ((e = upload_prec<double>(P, H, smu, gs::W64, gs::DEG64, 2.35 * gs::W64, s)) != hipSuccess) break;
         if (precision == GS_F32 || precision == GS_F32_MIXED)

@@ -83,6 +83,7 @@ struct Plan {
                                     // frequency row k of the grid is stored in row cr2 * (k % cr1) + k / cr1
     int32_t* perm = nullptr;        // [M] internal -> caller index
     int32_t* cell_start = nullptr;  // [ng^dim + 1] points sorted by cell (row-major)
+    int32_t* tile_order = nullptr;  // [tiles] 2D tiles in decreasing point count
     PrecData<double> d64;
     PrecData<float> d32;
     // solver state (device; FP64 vectors in internal point order)

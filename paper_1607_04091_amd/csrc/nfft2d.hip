@@ -41,6 +41,7 @@ struct TileGeo {
     const T* win;
     const int32_t* perm;
     const int32_t* cs;
+    const int32_t* order;   // workgroup -> tile, heaviest tiles first
     __device__ int grow(int k) const { return cr1 ? cr2 * (k & (cr1 - 1)) + k / cr1 : k; }
     __device__ int bcol(int r) const { return r < nb ? r : N - 1 - (r - nb); }
     __device__ int bchan(int r) const { return r < nb ? r : r + 1; }
@@ -94,7 +95,7 @@ __global__ void __launch_bounds__(256) interp_tile_kernel(TileGeo<T> g, const cx
                                                           int flags) {
     constexpr int TS = TILE_TS, PW = TS + W - 1;
     __shared__ cx<T> sG[PW * PW];
-    const int tile = blockIdx.x;
+    const int tile = g.order[blockIdx.x];
     const int q0 = g.cs[tile << (2 * g.lts)];
     const int q1 = g.cs[(tile + 1) << (2 * g.lts)];
     if (q0 == q1) return;
@@ -145,7 +146,7 @@ __global__ void __launch_bounds__(256) interp_bnd_kernel(TileGeo<T> g, const cx<
     __shared__ cx<T> sSR[NCH * PW];
     __shared__ cx<T> sSC[NCH * PW];
     __shared__ cx<T> sXC[NCH * NCH];
-    const int tile = blockIdx.x;
+    const int tile = g.order[blockIdx.x];
     const int q0 = g.cs[tile << (2 * g.lts)];
     const int q1 = g.cs[(tile + 1) << (2 * g.lts)];
     if (q0 == q1) return;
@@ -268,20 +269,36 @@ __global__ void adj_gather_kernel(TileGeo<T> g, const cx<T>* __restrict__ u, int
     vs[q] = v;
 }
 
-// staged bytes per workgroup (two workgroups fit the 160 KB of LDS of a CU)
-constexpr int ADJ_LDS_BUDGET = 72 * 1024;
-constexpr int adj_chb(int slot_bytes, int nrb, int lo, int hi, int mult) {
-    int c = ADJ_LDS_BUDGET / (nrb * slot_bytes);
+// Staged bytes per workgroup.  Workgroups of more than four wavefronts run two
+// per CU only while each holds at most about 48 KB of LDS (measured on MI355X),
+// so the staging areas stay below that.
+// The FP64 kernels run one workgroup per CU (registers), so they stage more.
+#ifndef GS_ADJ_INT_STAGE
+#define GS_ADJ_INT_STAGE (40 * 1024)
+#endif
+#ifndef GS_ADJ_BND_STAGE
+#define GS_ADJ_BND_STAGE (28 * 1024)
+#endif
+template <class T> constexpr int adj_int_stage() { return sizeof(T) == 8 ? 72 * 1024 : GS_ADJ_INT_STAGE; }
+template <class T> constexpr int adj_bnd_stage() { return sizeof(T) == 8 ? 64 * 1024 : GS_ADJ_BND_STAGE; }
+constexpr int adj_chb(int budget, int slot_bytes, int nrb, int lo, int hi, int mult) {
+    int c = budget / (nrb * slot_bytes);
     c = c > hi ? hi : c;
     c -= c % mult;
     return c < lo ? lo : c;
 }
 
-template <class T>
-struct alignas(16) AdjRec {
-    cx<T> v;   // conj(Dx Dy) sqrt(mu) u
-    int cy;    // tile-local cell column
-};
+// LDS row lengths padded to an odd number of 16-byte units, so that lanes
+// reading consecutive points with 16-byte loads spread over all banks
+constexpr int pad16odd(int bytes) {
+    int u = (bytes + 15) / 16;
+    return 16 * (u | 1);
+}
+constexpr int pow2ceil(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
 
 template <int W>
 struct IntShape {
@@ -291,14 +308,20 @@ struct IntShape {
 template <class T, int W, int NB>
 struct AdjIntLDS {
     static constexpr int TS = TILE_TS, PW = TS + W - 1, NRB = TS / ADJ_RB, NCH = 2 * NB;
-    static constexpr int SLOT = (int)(sizeof(AdjRec<T>) + 2 * W * sizeof(T) + NCH * sizeof(cx<T>));
+    // y taps stored rotated by the point's cell column: wyr[(b + cy) mod WR] = wy[b],
+    // so the thread owning padded column ply reads wyr[ply mod WR] without knowing cy
+    static constexpr int WR = pow2ceil(W);
+    static constexpr int LX = pad16odd(W * sizeof(T)) / sizeof(T);
+    static constexpr int LY = pad16odd(WR * sizeof(T)) / sizeof(T);
+    static constexpr int LC = NCH > 0 ? pad16odd(NCH * sizeof(cx<T>)) / sizeof(cx<T>) : 1;
+    static constexpr int SLOT = (int)(sizeof(cx<T>) + (LX + LY) * sizeof(T) + LC * sizeof(cx<T>));
     // at most one slot per thread: the next chunk's loads are held in registers
-    static constexpr int CHB = adj_chb(SLOT, NRB, 8, IntShape<W>::THREADS / NRB, 2), CH = NRB * CHB;
+    static constexpr int CHB = adj_chb(adj_int_stage<T>(), SLOT, NRB, 8, IntShape<W>::THREADS / NRB, 2), CH = NRB * CHB;
     struct Stage {
-        AdjRec<T> rec[CH];
-        T wx[CH][W];      // point-major so a thread reads a point's taps with wide loads
-        T wy[CH][W];
-        cx<T> cr[CH][NCH > 0 ? NCH : 1];   // conj(ax_r Dy) sqrt(mu) u: row-side values
+        cx<T> v[CH];                  // conj(Dx Dy) sqrt(mu) u
+        T wx[CH][LX];                 // point-major so a thread reads a point's taps with wide loads
+        T wy[CH][LY];
+        cx<T> cr[CH][LC];             // conj(ax_r Dy) sqrt(mu) u: row-side values
     };
     struct Out {
         cx<T> P[PW][PW];
@@ -336,7 +359,7 @@ __global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(Tile
     __shared__ __attribute__((aligned(16))) unsigned char lds_raw[L::bytes];
     auto& S = *reinterpret_cast<typename L::Stage*>(lds_raw);
 
-    const int tile = blockIdx.x, tid = threadIdx.x;
+    const int tile = g.order[blockIdx.x], tid = threadIdx.x;
     const int kbase = tile << (2 * g.lts);
     const int q0 = g.cs[kbase];
     const int t0y = (tile % g.ntx) << g.lts;
@@ -378,17 +401,15 @@ __global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(Tile
             T tx, ty;
             decode_pos2(pre.px, g.G, cxg, tx);
             decode_pos2(pre.py, g.G, cyg, ty);
-            AdjRec<T> r;
-            r.v = cmul(conjc(cmul(pre.dx, pre.dy)), pre.v);
-            r.cy = cyg - t0y;
-            S.rec[s] = r;
+            S.v[s] = cmul(conjc(cmul(pre.dx, pre.dy)), pre.v);
+            const int rot = cyg - t0y;
             T w[W];
             taps_all<T, W, DEG>(tx, g.win, w);
 #pragma unroll
             for (int j = 0; j < W; ++j) S.wx[s][j] = w[j];
             taps_all<T, W, DEG>(ty, g.win, w);
 #pragma unroll
-            for (int j = 0; j < W; ++j) S.wy[s][j] = w[j];
+            for (int j = 0; j < W; ++j) S.wy[s][(j + rot) & (L::WR - 1)] = w[j];
             if constexpr (NB > 0) {
                 const cx<T> vy = cmul(conjc(pre.dy), pre.v);
 #pragma unroll
@@ -406,12 +427,11 @@ __global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(Tile
                 const int pa = max(off[row * TS + cy_lo], R.lo), pb = min(off[row * TS + cy_hi + 1], R.hi);
                 for (int p = pa; p < pb; ++p) {
                     const int t = sb + p;
-                    const AdjRec<T> r = S.rec[t];
-                    const T w = S.wy[t][ply - r.cy];
+                    const T w = S.wy[t][ply & (L::WR - 1)];
+                    const cx<T> tv = cscale(S.v[t], w);
                     T wx[W];
 #pragma unroll
                     for (int a = 0; a < W; ++a) wx[a] = S.wx[t][a];
-                    const cx<T> tv = cscale(r.v, w);
 #pragma unroll
                     for (int a = 0; a < W; ++a) acc[rr + a] = cfma(acc[rr + a], tv, wx[a]);
                     if constexpr (NB > 0) {
@@ -473,7 +493,7 @@ struct AdjBndLDS {
     static constexpr int NBLK = (NE + 15) / 16;               // 16x16 MFMA blocks per side
     static constexpr int SLOT = (int)(W * sizeof(T) + NCH * sizeof(cx<T>) + 2 * NE * sizeof(T));
     // two threads per slot
-    static constexpr int CHB = adj_chb(SLOT, NRB, 4, 24, 4), CH = NRB * CHB;
+    static constexpr int CHB = adj_chb(adj_bnd_stage<T>(), SLOT, NRB, 4, 24, 4), CH = NRB * CHB;
     struct Stage {
         T wx[CH][W];
         cx<T> dc[CH][NCH];   // conj(ay_c Dx) sqrt(mu) u: column-side values
@@ -510,7 +530,7 @@ __global__ void __launch_bounds__(BND_THREADS) adj_boundary_kernel(TileGeo<T> g,
     __shared__ T cbuf[BND_CORW][LD * LD];
     auto& S = *reinterpret_cast<typename L::Stage*>(lds_raw);
 
-    const int tile = blockIdx.x, tid = threadIdx.x;
+    const int tile = g.order[blockIdx.x], tid = threadIdx.x;
     const int kbase = tile << (2 * g.lts);
     const int q0 = g.cs[kbase];
     for (int c = tid; c <= TS * TS; c += BND_THREADS) off[c] = g.cs[kbase + c] - q0;
@@ -609,10 +629,16 @@ __global__ void __launch_bounds__(BND_THREADS) adj_boundary_kernel(TileGeo<T> g,
                         accC[i] = czero<T>();
                         cur[i] = row;
                     }
-                    cx<T> s = accC[i];
-#pragma unroll 4
-                    for (int p = pa; p < pe; ++p) s = cfma(s, S.dc[sb + p][cc], S.wx[sb + p][ca]);
-                    accC[i] = s;
+                    // two interleaved partial sums (even and odd points), combined per segment
+                    cx<T> s0 = accC[i], s1 = czero<T>();
+                    int p = pa;
+#pragma unroll 2
+                    for (; p + 1 < pe; p += 2) {
+                        s0 = cfma(s0, S.dc[sb + p][cc], S.wx[sb + p][ca]);
+                        s1 = cfma(s1, S.dc[sb + p + 1][cc], S.wx[sb + p + 1][ca]);
+                    }
+                    if (p < pe) s0 = cfma(s0, S.dc[sb + p][cc], S.wx[sb + p][ca]);
+                    accC[i] = cadd(s0, s1);
                 }
             }
         } else if (!colw) {
@@ -762,7 +788,7 @@ TileGeo<T> make_tile_geo(const Plan& P) {
     g.ts = P.ts; g.lts = ilog2(P.ts); g.ntx = P.ng / P.ts;
     g.cr1 = P.cr1; g.cr2 = P.cr2;
     g.pos = d.pos; g.chx = d.chx; g.chy = d.chy; g.smu = d.smu; g.win = d.win;
-    g.perm = P.perm; g.cs = P.cell_start;
+    g.perm = P.perm; g.cs = P.cell_start; g.order = P.tile_order;
     return g;
 }
 
