@@ -276,11 +276,8 @@ __global__ void adj_gather_kernel(TileGeo<T> g, const cx<T>* __restrict__ u, int
 #ifndef GS_ADJ_INT_STAGE
 #define GS_ADJ_INT_STAGE (40 * 1024)
 #endif
-#ifndef GS_ADJ_BND_STAGE
-#define GS_ADJ_BND_STAGE (28 * 1024)
-#endif
 template <class T> constexpr int adj_int_stage() { return sizeof(T) == 8 ? 72 * 1024 : GS_ADJ_INT_STAGE; }
-template <class T> constexpr int adj_bnd_stage() { return sizeof(T) == 8 ? 64 * 1024 : GS_ADJ_BND_STAGE; }
+
 constexpr int adj_chb(int budget, int slot_bytes, int nrb, int lo, int hi, int mult) {
     int c = budget / (nrb * slot_bytes);
     c = c > hi ? hi : c;
@@ -475,25 +472,31 @@ __global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(Tile
 }
 
 // Column sides and corners of one tile (App. C, the remaining blocks of the
-// 2D matrix), with the same chunked staging as the interior kernel.
-//   waves [0, COLW):  column sides PC[c][x] = sum_m dc_c(m) wx_m[x - cx_m].  A
-//       wave sums, per cell row, B[c][a] = sum over the row's points of
-//       dc_c wx[a] with lane = (c, a), then adds B[c][a] to its own partial
-//       at (c, row + a).  All lanes walk the same points, so the work is
-//       balanced whatever the distribution of points.
-//   waves [COLW, COLW+CORW): corners sum_m conj(ax_r ay_c) sqrt(mu_m) u_m as a
-//       real 16x16 MFMA product over the chunk's slots.
-constexpr int BND_COLW = 4, BND_CORW = 2;
-constexpr int BND_THREADS = 64 * (BND_COLW + BND_CORW);
+// 2D matrix), with the same row-block chunked staging as the interior kernel.
+// Four wavefronts; each one
+//   * stages half-slots of the chunk (x taps and x channels, or the y channels),
+//   * walks two row blocks of the chunk for the column sides
+//     PC[c][x] = sum_m dc_c(m) wx_m[x - cx_m]: with lane = (c, a) it sums, per
+//     cell row, B[c][a] = sum over the row's points of dc_c wx[a] and adds B to
+//     its own partial at (c, row + a); all lanes walk the same points, so the
+//     work is balanced whatever the distribution of points,
+//   * runs a quarter of the corner products sum_m conj(ax_r ay_c) sqrt(mu_m) u_m
+//     as real 16x16x4 MFMA steps over the chunk's slots.
+// Workgroups of four wavefronts run two per CU with up to 80 KB of LDS each.
+constexpr int BND_WAVES = 4;
+constexpr int BND_THREADS = 64 * BND_WAVES;
+constexpr int BND_LDS = 76 * 1024;
 
 template <class T, int W, int NB>
 struct AdjBndLDS {
     static constexpr int TS = TILE_TS, PW = TS + W - 1, NRB = TS / ADJ_RB;
     static constexpr int NCH = 2 * NB, NE = 4 * NB;          // channels; real entries of e, f
     static constexpr int NBLK = (NE + 15) / 16;               // 16x16 MFMA blocks per side
+    static constexpr int LD = 16 * NBLK;
+    static constexpr int FIXED = (int)(4 * (TS * TS + 1) + BND_WAVES * NCH * PW * sizeof(cx<T>) +
+                                       BND_WAVES * LD * LD * sizeof(T));
     static constexpr int SLOT = (int)(W * sizeof(T) + NCH * sizeof(cx<T>) + 2 * NE * sizeof(T));
-    // two threads per slot
-    static constexpr int CHB = adj_chb(adj_bnd_stage<T>(), SLOT, NRB, 4, 24, 4), CH = NRB * CHB;
+    static constexpr int CHB = adj_chb(BND_LDS - FIXED, SLOT, NRB, 4, 32, 4), CH = NRB * CHB;
     struct Stage {
         T wx[CH][W];
         cx<T> dc[CH][NCH];   // conj(ay_c Dx) sqrt(mu) u: column-side values
@@ -512,101 +515,113 @@ struct BndPre {
     cx<T> ch[2 * NB];
 };
 
+__device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 template <class T, int W, int DEG, int NB>
 __global__ void __launch_bounds__(BND_THREADS) adj_boundary_kernel(TileGeo<T> g, const cx<T>* __restrict__ vs,
                                                                    cx<T>* __restrict__ partC, cx<T>* __restrict__ partX) {
     using L = AdjBndLDS<T, W, NB>;
     constexpr int TS = TILE_TS, RB = ADJ_RB, PW = L::PW, NRB = L::NRB, NCH = L::NCH, NE = L::NE;
     constexpr int CH = L::CH, CHB = L::CHB;
-    static_assert(2 * CH <= BND_THREADS, "one half slot per thread");
-    constexpr int NBLK = L::NBLK, LD = 16 * NBLK;
+    constexpr int NBLK = L::NBLK, LD = L::LD;
     constexpr int NPAIR = NCH * W, NPB = (NPAIR + 63) / 64;   // (channel, tap) lanes and their wave blocks
-    static_assert(NPB <= BND_COLW, "column-side lanes");
-    constexpr int RG = BND_COLW / NPB;                        // row-block groups
-    constexpr int NCHAIN = (NRB + RG - 1) / RG;               // row blocks per column-side wave
+    static_assert(NPB <= BND_WAVES, "column-side lanes");
+    constexpr int RG = BND_WAVES / NPB;                       // row-block groups
+    constexpr int NCHAIN = (NRB + RG - 1) / RG;               // row blocks per wavefront
+    constexpr int HPT = (2 * CH + BND_THREADS - 1) / BND_THREADS;   // half-slots per thread
     __shared__ int off[TS * TS + 1];
     __shared__ __attribute__((aligned(16))) unsigned char lds_raw[sizeof(typename L::Stage)];
-    __shared__ cx<T> PCw[BND_COLW][NCH][PW];
-    __shared__ T cbuf[BND_CORW][LD * LD];
+    __shared__ cx<T> PCw[BND_WAVES][NCH][PW];
+    __shared__ T cbuf[BND_WAVES][LD * LD];
+    __shared__ T swin[(W / 2) * (DEG + 1)];   // the W/2 tap polynomials the symmetric evaluation reads
     auto& S = *reinterpret_cast<typename L::Stage*>(lds_raw);
 
     const int tile = g.order[blockIdx.x], tid = threadIdx.x;
     const int kbase = tile << (2 * g.lts);
     const int q0 = g.cs[kbase];
+    // array bases as locals: the half-slot selection below is then a register select
+    const P_t<T>* __restrict__ gpos = g.pos;
+    const cx<T>* __restrict__ gchx = g.chx;
+    const cx<T>* __restrict__ gchy = g.chy;
     for (int c = tid; c <= TS * TS; c += BND_THREADS) off[c] = g.cs[kbase + c] - q0;
-    for (int e = tid; e < BND_COLW * NCH * PW; e += BND_THREADS) (&PCw[0][0][0])[e] = czero<T>();
+    for (int c = tid; c < (W / 2) * (DEG + 1); c += BND_THREADS) swin[c] = g.win[c];
+    for (int e = tid; e < BND_WAVES * NCH * PW; e += BND_THREADS) (&PCw[0][0][0])[e] = czero<T>();
     __syncthreads();
     const int nck = rb_chunks<CHB>(off);
     const size_t M = g.M;
     const int wave = tid >> 6, lane = tid & 63;
-    const bool colw = wave < BND_COLW;
     // column-side lane roles
     const int pb = wave % NPB, rg = wave / NPB;
     const int pair = pb * 64 + lane;
-    const bool colact = colw && rg < RG && pair < NPAIR;
+    const bool colact = rg < RG && pair < NPAIR;
     const int cc = pair / W, ca = pair - cc * W;
     cx<T> accC[NCHAIN];
-    int cur[NCHAIN];
+    int cur[NCHAIN];     // cell row being summed per row block (uniform), -1 before the first
 #pragma unroll
     for (int i = 0; i < NCHAIN; ++i) {
         accC[i] = czero<T>();
         cur[i] = -1;
     }
     // corner lane roles
-    const int cw = wave - BND_COLW;
     const int li = lane & 15, kk = lane >> 4;
     typename Mfma<T>::acc accM[NBLK * NBLK];
 #pragma unroll
     for (int b = 0; b < NBLK * NBLK; ++b) accM[b] = Mfma<T>::zero();
 
-    BndPre<T, NB> pre;
-    const int half = tid >= CH, hs = tid - half * CH;   // slot hs, half 0 or 1
+    BndPre<T, NB> pre[HPT];
     auto load = [&](int k) {
-        pre.p = hs < CH ? rb_point<CHB>(off, k, hs) : -1;
-        if (pre.p < 0) return;
-        const int q = q0 + pre.p;
-        pre.v = vs[q];
-        if (half == 0) {
-            pre.px = g.pos[q];
 #pragma unroll
-            for (int r = 0; r < NCH; ++r) pre.ch[r] = g.chx[(size_t)(r < NB ? r : r + 1) * M + q];
-        } else {
-            pre.d = g.chx[NB * M + q];
+        for (int j = 0; j < HPT; ++j) {
+            const int h = tid + j * BND_THREADS;
+            pre[j].p = h < 2 * CH ? rb_point<CHB>(off, k, h >> 1) : -1;
+            if (pre[j].p < 0) continue;
+            const int q = q0 + pre[j].p;
+            const bool xh = (h & 1) == 0;
+            pre[j].v = vs[q];
+            if (xh)
+                pre[j].px = gpos[q];
+            else
+                pre[j].d = gchx[NB * M + q];
+            const cx<T>* __restrict__ chp = xh ? gchx : gchy;
 #pragma unroll
-            for (int r = 0; r < NCH; ++r) pre.ch[r] = g.chy[(size_t)(r < NB ? r : r + 1) * M + q];
+            for (int r = 0; r < NCH; ++r) pre[j].ch[r] = chp[(size_t)(r < NB ? r : r + 1) * M + q];
         }
     };
     if (nck > 0) load(0);
 
     for (int k = 0; k < nck; ++k) {
         if (k) __syncthreads();
-        if (hs < CH) {
-            const int s = hs;
-            if (pre.p < 0) {
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+            const int h = tid + j * BND_THREADS;
+            if (h >= 2 * CH) continue;
+            const int s = h >> 1;
+            const BndPre<T, NB>& P = pre[j];
+            if (P.p < 0) {
                 // empty slots enter the corner product as zeros
 #pragma unroll
-                for (int i = 0; i < NE; ++i) (half == 0 ? S.e[s][i] : S.f[s][i]) = T(0);
-            } else if (half == 0) {
+                for (int i = 0; i < NE; ++i) ((h & 1) == 0 ? S.e[s][i] : S.f[s][i]) = T(0);
+            } else if ((h & 1) == 0) {
                 int cxg;
                 T tx;
-                decode_pos2(pre.px, g.G, cxg, tx);
+                decode_pos2(P.px, g.G, cxg, tx);
                 T w[W];
-                taps_all<T, W, DEG>(tx, g.win, w);
+                taps_all<T, W, DEG>(tx, swin, w);
 #pragma unroll
-                for (int j = 0; j < W; ++j) S.wx[s][j] = w[j];
+                for (int jj = 0; jj < W; ++jj) S.wx[s][jj] = w[jj];
 #pragma unroll
                 for (int r = 0; r < NCH; ++r) {
-                    const cx<T> e = cmul(conjc(pre.ch[r]), pre.v);
+                    const cx<T> e = cmul(conjc(P.ch[r]), P.v);
                     S.e[s][r] = e.x;
                     S.e[s][NCH + r] = e.y;
                 }
             } else {
-                const cx<T> vx = cmul(conjc(pre.d), pre.v);
+                const cx<T> vx = cmul(conjc(P.d), P.v);
 #pragma unroll
                 for (int r = 0; r < NCH; ++r) {
-                    S.dc[s][r] = cmul(conjc(pre.ch[r]), vx);
-                    S.f[s][r] = pre.ch[r].x;
-                    S.f[s][NCH + r] = -pre.ch[r].y;
+                    S.dc[s][r] = cmul(conjc(P.ch[r]), vx);
+                    S.f[s][r] = P.ch[r].x;
+                    S.f[s][NCH + r] = -P.ch[r].y;
                 }
             }
         }
@@ -619,42 +634,51 @@ __global__ void __launch_bounds__(BND_THREADS) adj_boundary_kernel(TileGeo<T> g,
                 if (b >= NRB) continue;
                 const RbRange R = rb_range<CHB>(off, b, k);
                 const int sb = b * CHB - R.lo;
-#pragma unroll
-                for (int rr = 0; rr < RB; ++rr) {
-                    const int row = b * RB + rr;
-                    const int pa = max(off[row * TS], R.lo), pe = min(off[row * TS + TS], R.hi);
-                    if (pa >= pe) continue;
+                int p = uniform(R.lo);
+                const int hi = uniform(R.hi);
+                while (p < hi) {
+                    // the cell row holding point p; rows are walked in increasing order
+                    int row = cur[i] < 0 ? b * RB : cur[i];
+                    while (uniform(off[(row + 1) * TS]) <= p) ++row;
                     if (row != cur[i]) {
                         if (cur[i] >= 0) PCw[wave][cc][cur[i] + ca] = cadd(PCw[wave][cc][cur[i] + ca], accC[i]);
                         accC[i] = czero<T>();
                         cur[i] = row;
                     }
-                    // two interleaved partial sums (even and odd points), combined per segment
-                    cx<T> s0 = accC[i], s1 = czero<T>();
-                    int p = pa;
-#pragma unroll 2
-                    for (; p + 1 < pe; p += 2) {
-                        s0 = cfma(s0, S.dc[sb + p][cc], S.wx[sb + p][ca]);
-                        s1 = cfma(s1, S.dc[sb + p + 1][cc], S.wx[sb + p + 1][ca]);
+                    const int pe = min(hi, uniform(off[(row + 1) * TS]));
+                    // four interleaved partial sums, eight points per step: the loads of
+                    // a step are issued together
+                    cx<T> s0 = accC[i], s1 = czero<T>(), s2 = czero<T>(), s3 = czero<T>();
+                    for (; p + 7 < pe; p += 8) {
+                        cx<T> d[8];
+                        T w[8];
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            d[j] = S.dc[sb + p + j][cc];
+                            w[j] = S.wx[sb + p + j][ca];
+                        }
+                        s0 = cfma(cfma(s0, d[0], w[0]), d[4], w[4]);
+                        s1 = cfma(cfma(s1, d[1], w[1]), d[5], w[5]);
+                        s2 = cfma(cfma(s2, d[2], w[2]), d[6], w[6]);
+                        s3 = cfma(cfma(s3, d[3], w[3]), d[7], w[7]);
                     }
-                    if (p < pe) s0 = cfma(s0, S.dc[sb + p][cc], S.wx[sb + p][ca]);
-                    accC[i] = cadd(s0, s1);
+                    for (; p < pe; ++p) s0 = cfma(s0, S.dc[sb + p][cc], S.wx[sb + p][ca]);
+                    accC[i] = cadd(cadd(s0, s1), cadd(s2, s3));
                 }
             }
-        } else if (!colw) {
-            // C = E F^T over the chunk's slots, 4 slots per MFMA step
-            for (int s4 = cw; s4 < CH / 4; s4 += BND_CORW) {
-                const int t = 4 * s4 + kk;
+        }
+        // this wavefront's share of the corner steps, 4 slots per MFMA step
+        for (int s4 = wave; s4 < CH / 4; s4 += BND_WAVES) {
+            const int t = 4 * s4 + kk;
 #pragma unroll
-                for (int bi = 0; bi < NBLK; ++bi) {
-                    const int ie = bi * 16 + li;
-                    const T av = ie < NE ? S.e[t][ie] : T(0);
+            for (int bi = 0; bi < NBLK; ++bi) {
+                const int ie = bi * 16 + li;
+                const T av = ie < NE ? S.e[t][ie] : T(0);
 #pragma unroll
-                    for (int bj = 0; bj < NBLK; ++bj) {
-                        const int jf = bj * 16 + li;
-                        const T bv = jf < NE ? S.f[t][jf] : T(0);
-                        accM[bi * NBLK + bj] = Mfma<T>::step(av, bv, accM[bi * NBLK + bj]);
-                    }
+                for (int bj = 0; bj < NBLK; ++bj) {
+                    const int jf = bj * 16 + li;
+                    const T bv = jf < NE ? S.f[t][jf] : T(0);
+                    accM[bi * NBLK + bj] = Mfma<T>::step(av, bv, accM[bi * NBLK + bj]);
                 }
             }
         }
@@ -663,24 +687,23 @@ __global__ void __launch_bounds__(BND_THREADS) adj_boundary_kernel(TileGeo<T> g,
 #pragma unroll
         for (int i = 0; i < NCHAIN; ++i)
             if (cur[i] >= 0) PCw[wave][cc][cur[i] + ca] = cadd(PCw[wave][cc][cur[i] + ca], accC[i]);
-    } else if (!colw) {
-#pragma unroll
-        for (int bi = 0; bi < NBLK; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < NBLK; ++bj)
-#pragma unroll
-                for (int vv = 0; vv < 4; ++vv) {
-                    const int row = bi * 16 + Mfma<T>::row(lane, vv), col = bj * 16 + (lane & 15);
-                    cbuf[cw][row * LD + col] = accM[bi * NBLK + bj][vv];
-                }
     }
+#pragma unroll
+    for (int bi = 0; bi < NBLK; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < NBLK; ++bj)
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                const int row = bi * 16 + Mfma<T>::row(lane, vv), col = bj * 16 + (lane & 15);
+                cbuf[wave][row * LD + col] = accM[bi * NBLK + bj][vv];
+            }
     __syncthreads();
-    // wave partials in fixed order
+    // wavefront partials in fixed order
     cx<T>* pC = partC + (size_t)tile * NCH * PW;
     for (int e = tid; e < NCH * PW; e += BND_THREADS) {
         cx<T> s = (&PCw[0][0][0])[e];
 #pragma unroll
-        for (int w = 1; w < BND_COLW; ++w) s = cadd(s, (&PCw[w][0][0])[e]);
+        for (int w = 1; w < BND_WAVES; ++w) s = cadd(s, (&PCw[w][0][0])[e]);
         pC[e] = s;
     }
     cx<T>* pX = partX + (size_t)tile * NCH * NCH;
@@ -688,7 +711,7 @@ __global__ void __launch_bounds__(BND_THREADS) adj_boundary_kernel(TileGeo<T> g,
         const int r = e / NCH, c = e - r * NCH;
         T re = T(0), im = T(0);
 #pragma unroll
-        for (int w = 0; w < BND_CORW; ++w) {
+        for (int w = 0; w < BND_WAVES; ++w) {
             re += cbuf[w][r * LD + c] - cbuf[w][(NCH + r) * LD + NCH + c];
             im += cbuf[w][r * LD + NCH + c] + cbuf[w][(NCH + r) * LD + c];
         }
