@@ -151,10 +151,19 @@ __device__ inline bool grid_row_active(int q, int ng, int N, int nb) {
     return k >= -(N >> 1) + nb && k < (N >> 1) - nb;
 }
 
-// prune_in: inactive input rows are zero (forward); prune_out: inactive output rows are not stored (adjoint)
-template <class T, int R1, int R2, int DIR>
-__global__ void __launch_bounds__(256) colfft_pass1(cx<T>* __restrict__ grid, const cx<T>* __restrict__ tw, int N,
-                                                    int nb, int prune_in) {
+// input of a column pass 1: element (row q, column c) of the grid, inactive rows
+// read as zero when prune is set (forward)
+template <class T>
+struct GridLoad {
+    const cx<T>* grid;
+    int L, N, nb, prune;
+    __device__ cx<T> operator()(int q, int col) const {
+        return (prune && !grid_row_active(q, L, N, nb)) ? czero<T>() : grid[(size_t)q * L + col];
+    }
+};
+
+template <class T, int R1, int R2, int DIR, class Load>
+__global__ void __launch_bounds__(256) colfft_pass1(Load ld, cx<T>* __restrict__ grid, const cx<T>* __restrict__ tw) {
     constexpr int L = R1 * R2;
     __shared__ cx<T> stw[L];
     for (int e = threadIdx.x; e < L; e += 256) stw[e] = tw[e];
@@ -163,10 +172,7 @@ __global__ void __launch_bounds__(256) colfft_pass1(cx<T>* __restrict__ grid, co
     const int n2 = blockIdx.y * 4 + (threadIdx.x >> 6);
     cx<T> v[R1];
 #pragma unroll
-    for (int n1 = 0; n1 < R1; ++n1) {
-        const int q = R2 * n1 + n2;
-        v[n1] = (prune_in && !grid_row_active(q, L, N, nb)) ? czero<T>() : grid[(size_t)q * L + col];
-    }
+    for (int n1 = 0; n1 < R1; ++n1) v[n1] = ld(R2 * n1 + n2, col);
     reg_fft<T, R1, DIR>(v, stw, L / R1);
 #pragma unroll
     for (int k1 = 0; k1 < R1; ++k1) {
@@ -196,26 +202,40 @@ __global__ void __launch_bounds__(256) colfft_pass2(cx<T>* __restrict__ grid, co
     }
 }
 
-template <class T, int R1, int R2, int DIR>
-inline hipError_t launch_colfft(cx<T>* grid, const cx<T>* tw, int N, int nb, int prune_in, int prune_out,
+// both passes; Load supplies the input of pass 1 (prune_out: inactive output rows are not stored)
+template <class T, int R1, int R2, int DIR, class Load>
+inline hipError_t launch_colfft(const Load& ld, cx<T>* grid, const cx<T>* tw, int N, int nb, int prune_out,
                                 hipStream_t s) {
     constexpr int L = R1 * R2;
-    hipLaunchKernelGGL((colfft_pass1<T, R1, R2, DIR>), dim3(L / 64, R2 / 4), dim3(256), 0, s, grid, tw, N, nb,
-                       prune_in);
+    hipLaunchKernelGGL((colfft_pass1<T, R1, R2, DIR, Load>), dim3(L / 64, R2 / 4), dim3(256), 0, s, ld, grid, tw);
     GS_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL((colfft_pass2<T, R1, R2, DIR>), dim3(L / 64, R1 / 4), dim3(256), 0, s, grid, tw, N, nb,
                        prune_out);
     return hipGetLastError();
 }
 
-template <class T, int DIR>
-inline hipError_t launch_colfft_split(int cr1, int ng, cx<T>* grid, const cx<T>* tw, int N, int nb, int prune_in,
+// the column split of Plan::cr1 for grids of side ng; LoadF(L) builds the pass-1 input
+template <class T, int DIR, class LoadF>
+inline hipError_t launch_colfft_split(int cr1, int ng, const LoadF& mk, cx<T>* grid, const cx<T>* tw, int N, int nb,
                                       int prune_out, hipStream_t s) {
-    if (ng == 1024 && cr1 == 32) return launch_colfft<T, 32, 32, DIR>(grid, tw, N, nb, prune_in, prune_out, s);
-    if (ng == 512 && cr1 == 32) return launch_colfft<T, 32, 16, DIR>(grid, tw, N, nb, prune_in, prune_out, s);
-    if (ng == 256 && cr1 == 16) return launch_colfft<T, 16, 16, DIR>(grid, tw, N, nb, prune_in, prune_out, s);
+    if (ng == 1024 && cr1 == 32) return launch_colfft<T, 32, 32, DIR>(mk(1024), grid, tw, N, nb, prune_out, s);
+    if (ng == 512 && cr1 == 32) return launch_colfft<T, 32, 16, DIR>(mk(512), grid, tw, N, nb, prune_out, s);
+    if (ng == 256 && cr1 == 16) return launch_colfft<T, 16, 16, DIR>(mk(256), grid, tw, N, nb, prune_out, s);
     return hipErrorInvalidValue;
 }
+
+// a pair of transform sets in one launch: transforms [0, na) of a, then those of b
+template <class T, class A, class B>
+struct OpJoin {
+    A a;
+    B b;
+    int na;
+    __device__ cx<T> load(int t, int i) const { return t < na ? a.load(t, i) : b.load(t - na, i); }
+    __device__ void store(int t, int k, cx<T> v) const {
+        if (t < na) a.store(t, k, v);
+        else b.store(t - na, k, v);
+    }
+};
 
 // columns per workgroup for strided (column) passes: keep LDS <= 32 KB
 template <class T>

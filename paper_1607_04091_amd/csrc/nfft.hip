@@ -543,17 +543,22 @@ hipError_t launch_apply_T(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hi
     const Geo<T> g = make_geo<T>(P);
     const int N = P.N, nb = P.nb, ng = P.ng;
     if (P.dim == 2) {
-        GS_TIMED(K_FFT_ROWS_T, GS_HIP_TRY((launch_fft<T, -1>(OpT2Rows<T>{x, d.grid, d.sr, d.deap, N, nb, ng}, N, ng, 1,
-                                                           d.tw, ng, s))));
-        if (P.cr1)
-            GS_TIMED(K_FFT_COLS_T, GS_HIP_TRY((launch_colfft_split<T, -1>(P.cr1, ng, d.grid, d.tw, N, nb, 1, 0, s))));
-        else
+        const OpT2Rows<T> rows{x, d.grid, d.sr, d.deap, N, nb, ng};
+        if (nb) {
+            // the 2nb side-column transforms share the row launch
+            using J = OpJoin<T, OpT2Rows<T>, OpT2SideCols<T>>;
+            GS_TIMED(K_FFT_ROWS_T, GS_HIP_TRY((launch_fft<T, -1>(J{rows, OpT2SideCols<T>{x, d.sc, d.deap, N, nb, ng}, N},
+                                                               N + 2 * nb, ng, 1, d.tw, ng, s))));
+        } else {
+            GS_TIMED(K_FFT_ROWS_T, GS_HIP_TRY((launch_fft<T, -1>(rows, N, ng, 1, d.tw, ng, s))));
+        }
+        if (P.cr1) {
+            auto mk = [&](int L) { return GridLoad<T>{d.grid, L, N, nb, 1}; };
+            GS_TIMED(K_FFT_COLS_T, GS_HIP_TRY((launch_colfft_split<T, -1>(P.cr1, ng, mk, d.grid, d.tw, N, nb, 0, s))));
+        } else {
             GS_TIMED(K_FFT_COLS_T, GS_HIP_TRY((launch_fft<T, -1>(OpCols<T>{d.grid, N, nb, ng, 1}, ng, ng,
                                                                col_batch<T>(ng), d.tw, ng, s))));
-        if (nb)
-            GS_TIMED(K_FFT_SIDECOLS_T,
-                     GS_HIP_TRY((launch_fft<T, -1>(OpT2SideCols<T>{x, d.sc, d.deap, N, nb, ng}, 2 * nb, ng,
-                                                   1, d.tw, ng, s))));
+        }
     } else {
         const Pad1<T> pad{x, d.deap, N, ng};
         if (ng <= FFT_MAX_LDS) {
@@ -577,18 +582,21 @@ hipError_t launch_apply_TH(const Plan& P, const cx<T>* u, cx<T>* x, int flags, h
     const int N = P.N, nb = P.nb, ng = P.ng;
     if (P.dim == 2 && P.ts == TILE) {
         GS_HIP_TRY(adjoint2d_tile<T>(P, u, x, flags, s));
-        if (P.cr1)
-            GS_TIMED(K_FFT_COLS_TH, GS_HIP_TRY((launch_colfft_split<T, +1>(P.cr1, ng, d.grid, d.tw, N, nb, 0, 1, s))));
-        else
+        if (P.cr1) {
+            auto mk = [&](int L) { return GridLoad<T>{d.grid, L, N, nb, 0}; };
+            GS_TIMED(K_FFT_COLS_TH, GS_HIP_TRY((launch_colfft_split<T, +1>(P.cr1, ng, mk, d.grid, d.tw, N, nb, 1, s))));
+        } else {
             GS_TIMED(K_FFT_COLS_TH, GS_HIP_TRY((launch_fft<T, +1>(OpCols<T>{d.grid, N, nb, ng, 0}, ng, ng,
                                                                 col_batch<T>(ng), d.tw, ng, s))));
-        GS_TIMED(K_FFT_ROWS_TH,
-                 GS_HIP_TRY((launch_fft<T, +1>(OpTH2Rows<T>{d.grid, d.sr, x, d.deap, N, nb, ng, P.cr1, P.cr2}, N, ng,
-                                               1, d.tw, ng, s))));
-        if (nb)
-            GS_TIMED(K_FFT_SIDECOLS_TH,
-                     GS_HIP_TRY((launch_fft<T, +1>(OpTH2SideCols<T>{d.sc, x, d.deap, N, nb, ng}, 2 * nb, ng,
-                                                   1, d.tw, ng, s))));
+        }
+        const OpTH2Rows<T> rows{d.grid, d.sr, x, d.deap, N, nb, ng, P.cr1, P.cr2};
+        if (nb) {
+            using J = OpJoin<T, OpTH2Rows<T>, OpTH2SideCols<T>>;
+            GS_TIMED(K_FFT_ROWS_TH, GS_HIP_TRY((launch_fft<T, +1>(J{rows, OpTH2SideCols<T>{d.sc, x, d.deap, N, nb, ng}, N},
+                                                                N + 2 * nb, ng, 1, d.tw, ng, s))));
+        } else {
+            GS_TIMED(K_FFT_ROWS_TH, GS_HIP_TRY((launch_fft<T, +1>(rows, N, ng, 1, d.tw, ng, s))));
+        }
         return hipSuccess;
     }
     cx<T>* v = d.vbuf;
