@@ -270,11 +270,12 @@ __global__ void adj_gather_kernel(TileGeo<T> g, const cx<T>* __restrict__ u, int
 }
 
 // Staged bytes per workgroup.  Workgroups of more than four wavefronts run two
-// per CU only while each holds at most about 48 KB of LDS (measured on MI355X),
-// so the staging areas stay below that.
+// per CU only while each holds at most about 52 KB of LDS (measured on MI355X:
+// 51 KB runs two per CU, 59 KB one), so the interior kernel's staging area
+// stays below that.
 // The FP64 kernels run one workgroup per CU (registers), so they stage more.
 #ifndef GS_ADJ_INT_STAGE
-#define GS_ADJ_INT_STAGE (40 * 1024)
+#define GS_ADJ_INT_STAGE (48 * 1024)
 #endif
 template <class T> constexpr int adj_int_stage() { return sizeof(T) == 8 ? 72 * 1024 : GS_ADJ_INT_STAGE; }
 
