@@ -10,9 +10,11 @@ One step = one apply pair y = A x, z = A^H u through the C ABI.  Also
 reported: FP64 apply pairs/s, per-kernel times (HIP events on the launch
 stream), the roofline of the dominant kernel, the plan ("init") time,
 wall time to relative normal residual 1e-6 for the plain FP64 and the
-FP32-mixed CGLS, and the FP64 CPU oracle timed on a bounded sample.
+FP32-mixed CGLS, the batched solve of 64 uneven 2D problems (against the
+same solves one after the other), and the FP64 CPU oracle timed on a
+bounded sample.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--no-cpu] [--no-batch]
 """
 from __future__ import annotations
 
@@ -100,6 +102,59 @@ def oracle_baseline(pts, mu, J, p, sample, M):
                       f"columns + BLAS), {t:.2f} s, scaled linearly to all points"}
 
 
+def batch_c4(gs, torch, dev, n_problems):
+    """The batched workload: n_problems independent 2D problems (seeds
+    4000 + b; J 6..9, db2/db4, jittered grid or spiral, M = 2..4 x 4^J),
+    FP32-mixed plans, y = T x0 (FP64 apply of the phantom), constant area
+    weights.  Times the batched solve against the same solves run one after
+    the other, and checks that each problem's result agrees."""
+    from concurrent.futures import ThreadPoolExecutor
+    from workloads import config_c4_problem
+    t0 = time.time()
+    with ThreadPoolExecutor(8) as ex:
+        cfgs = list(ex.map(lambda b: config_c4_problem(b, "area"), range(n_problems)))
+    plans, ys = [], []
+    for c in cfgs:
+        pl = gs.gs_plan(2, c["J"], c["p"], c["xi"], c["mu"], precision=gs.GS_F32_MIXED)
+        y = torch.empty(pl.M, dtype=torch.complex128, device=dev)
+        pl.apply_T(torch.from_numpy(c["x0"]).to(dev), y, f64=True)
+        plans.append(pl)
+        ys.append(y)
+    torch.cuda.synchronize()
+    total_m = sum(pl.M for pl in plans)
+    log(f"[bench] batch: {n_problems} problems, {total_m} points, inputs and plans {time.time() - t0:.1f} s")
+    kw = dict(rel_tol=1e-6, max_iter=1000, refine_fp64=True, max_restarts=3, check_every=10)
+    gs.gs_solve_batch(plans, ys, rel_tol=1e-6, max_iter=2, check_every=1, n_streams=1)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lone = [pl.solve(y, **kw)[1] for pl, y in zip(plans, ys)]
+    torch.cuda.synchronize()
+    t_lone = time.perf_counter() - t0
+    res = {}
+    for ns in (1, 0):
+        t0 = time.perf_counter()
+        _, infos = gs.gs_solve_batch(plans, ys, n_streams=ns, **kw)
+        torch.cuda.synchronize()
+        res[ns] = (time.perf_counter() - t0, infos)
+    t_batch, infos = res[0]
+    same = all(a["iterations"] == b["iterations"] and a["rel_residual"] == b["rel_residual"]
+               for a, b in zip(lone, infos))
+    out = {"problems": n_problems, "points": int(total_m), "weights": "constant area per point",
+           "wall_s": round(t_batch, 4), "wall_s_one_stream": round(res[1][0], 4),
+           "lone_sequential_wall_s": round(t_lone, 4), "speedup_vs_lone": round(t_lone / t_batch, 3),
+           "converged": sum(i["status"] == gs.GS_OK for i in infos),
+           "iterations_max": max(i["iterations"] for i in infos),
+           "iterations_sum": sum(i["iterations"] for i in infos),
+           "max_rel_residual_fp64": max(i["rel_residual_fp64"] for i in infos),
+           "equals_lone_solves": same}
+    log(f"[bench] batch solve: {t_batch:.3f} s (one stream {res[1][0]:.3f} s), lone solves {t_lone:.3f} s, "
+        f"{out['converged']}/{n_problems} converged, max iterations {out['iterations_max']}, "
+        f"equal to lone: {same}")
+    for pl in plans:
+        pl.destroy()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +162,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-problems", type=int, default=64)
     ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--arms", type=int, default=64)
     ap.add_argument("--per-arm", type=int, default=16384)
@@ -232,6 +289,8 @@ def main():
             if pl is not plan:
                 pl.destroy()
         solve["warm_start"] = None
+        if not args.no_batch:
+            solve["batched_c4"] = batch_c4(gs, torch, dev, args.batch_problems)
 
     cpu = None
     if not args.no_cpu:

@@ -131,9 +131,38 @@ typedef struct gs_solve_info {
  * reductions are FP64 and device-resident; applies run in the plan's
  * precision.  Returns GS_OK, GS_NOT_CONVERGED (x = last iterate) or an error.
  * Synchronizes `stream` every opts->check_every iterations.
+ * Mixed form (GS_F32_MIXED with refine_fp64): the FP32-apply recurrence stops
+ * when its normal residual rises 100x above its smallest value (it has passed
+ * the FP32 accuracy floor) or breaks down; the FP64 residual is then
+ * recomputed and the recurrence restarted from x (at most max_restarts
+ * times).  Status follows the FP64 residual: GS_OK at or below rel_tol, else
+ * GS_NOT_CONVERGED; GS_ERR_BREAKDOWN only if it is not finite.
  */
 int gs_solve(const gs_plan_t* plan, const void* y, void* x, const gs_solve_opts* opts,
              gs_solve_info* info, void* stream);
+
+/*
+ * gs_solve_batch -- many independent weighted LS problems (Sec. 2, Sec. 4.1),
+ * each with its own plan (sizes, point sets and precisions may differ), solved
+ * together.  plans[i], y[i], x[i] follow gs_solve's layouts; plans and x
+ * buffers must be pairwise distinct (each problem owns its plan's work
+ * vectors).  One options struct serves every problem; opts->history must be
+ * NULL.  infos: HOST array of `count` results.
+ *
+ * Each problem's CGLS iteration is captured once as a HIP graph; the graphs
+ * of the problems still running are launched round after round on up to
+ * n_streams internal streams (problems placed heaviest first), and every
+ * opts->check_every rounds one host synchronization reads all stop flags and
+ * retires the problems that are done.  n_streams = 0 picks the stream count
+ * (1, 2, 4, 8, capped at count) from short timed trial rounds; otherwise
+ * 1..64.  The iterates are those gs_solve produces (same kernels, same
+ * order), so per problem the result equals gs_solve's bit for bit.  The
+ * internal streams wait for `stream` on entry; the call returns after all
+ * work is done.  Returns GS_OK when every problem converged, GS_NOT_CONVERGED
+ * when some did not (see infos[i].status), or the first error.
+ */
+int gs_solve_batch(const gs_plan_t* const* plans, int count, const void* const* y, void* const* x,
+                   const gs_solve_opts* opts, gs_solve_info* infos, int n_streams, void* stream);
 
 /* Releases every resource of the plan (NULL is ignored). */
 void gs_destroy(gs_plan_t* plan);

@@ -10,17 +10,24 @@
 // precision.  Reductions are two-stage with a fixed block count and a fixed
 // summation order, so results are bitwise reproducible.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <vector>
 
 #include "common.hpp"
+#include "prof.hpp"
 
 namespace gs {
 
 constexpr int RB = 512;      // reduction blocks (fixed -> deterministic)
 constexpr int RT = 256;      // threads per reduction block
 
-enum Scal { S_GAMMA = 0, S_DELTA, S_ALPHA, S_REF, S_TOL2, S_DONE, S_BREAK, S_ITER, S_REF64, S_NSCAL = 16 };
+// S_GMIN: smallest gamma of the current run; S_GROW: stall factor (0 = off);
+// S_STALL: the run stopped because gamma rose above S_GROW * S_GMIN
+enum Scal {
+    S_GAMMA = 0, S_DELTA, S_ALPHA, S_REF, S_TOL2, S_DONE, S_BREAK, S_ITER, S_REF64, S_GMIN, S_GROW, S_STALL,
+    S_NSCAL = 16
+};
 
 template <class T> __device__ inline cx<double> to64(cx<T> v) { return mk<double>((double)v.x, (double)v.y); }
 
@@ -112,6 +119,8 @@ __global__ void start_scalars_kernel(double* __restrict__ scal, const double* __
         if (set_ref) scal[S_REF] = sqrt(g);
         scal[S_ITER] = 0;
         scal[S_BREAK] = 0;
+        scal[S_GMIN] = g;
+        scal[S_STALL] = 0;
         const double ref = scal[S_REF];
         scal[S_DONE] = (ref == 0.0 || g <= scal[S_TOL2] * ref * ref) ? 1.0 : 0.0;
         if (hist && hist_len > 0) hist[0] = ref > 0 ? sqrt(g) / ref : 0.0;
@@ -135,7 +144,7 @@ __global__ void __launch_bounds__(RT) update_xr_kernel(double* __restrict__ scal
     const double delta = sum_partials(red, sh);
     if (scal[S_DONE] != 0.0) return;
     const double alpha = scal[S_GAMMA] / delta;
-    if (!(delta > 0.0) || !isfinite(alpha)) {
+    if (!(delta > 0.0) || !isfinite(delta) || !isfinite(alpha)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_BREAK] = 1.0;
         return;
     }
@@ -198,7 +207,15 @@ __global__ void step_scalars_kernel(double* __restrict__ scal, const double* __r
     scal[S_ITER] = it;
     const double ref = scal[S_REF];
     if (hist && (int)it < hist_len) hist[(int)it] = sqrt(gnew) / ref;
-    if (gnew <= scal[S_TOL2] * ref * ref) scal[S_DONE] = 1.0;
+    if (gnew <= scal[S_TOL2] * ref * ref) {
+        scal[S_DONE] = 1.0;
+    } else if (scal[S_GROW] > 0.0 && !(gnew <= scal[S_GROW] * scal[S_GMIN])) {
+        // reduced-precision recurrence past its accuracy floor: stop it here
+        scal[S_STALL] = 1.0;
+        scal[S_BREAK] = 1.0;
+        scal[S_DONE] = 1.0;
+    }
+    scal[S_GMIN] = fmin(scal[S_GMIN], gnew);
 }
 
 __global__ void set_scalar_kernel(double* __restrict__ scal, int idx, double v) {
@@ -343,9 +360,9 @@ hipError_t cgls_run(const Plan& P, cx<double>* x, hipStream_t st, int budget, in
     return hipSuccess;
 }
 
+// b, reference ||A^H b||, initial residual (x0 = 0 or warm start), s, gamma, p
 template <class T>
-int solve_impl(const Plan& P, const cx<double>* y, cx<double>* x, const gs_solve_opts& opt, gs_solve_info& info,
-               hipStream_t st) {
+int solve_setup(const Plan& P, const cx<double>* y, cx<double>* x, const gs_solve_opts& opt, hipStream_t st) {
     const int64_t nx = P.dim == 2 ? (int64_t)P.N * P.N : P.N;
     const int64_t M = P.M;
     Ops<T> o{P};
@@ -353,6 +370,10 @@ int solve_impl(const Plan& P, const cx<double>* y, cx<double>* x, const gs_solve
     double* hist = opt.history ? P.hist : nullptr;
     const int hist_len = std::min(P.hist_len, opt.history_len);
     hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, st, P.scal, (int)S_TOL2, opt.rel_tol * opt.rel_tol);
+    // FP32 applies (mixed form) stop when the normal residual has grown 100x
+    // over its smallest value; the FP64 refinement then restarts them
+    hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, st, P.scal, (int)S_GROW,
+                       std::is_same<T, float>::value ? 1e4 : 0.0);
     hipLaunchKernelGGL((init_b_kernel<T>), dim3(nb256(M)), dim3(256), 0, st, y, P.perm, P.smu64, M, P.b, P.r,
                        o.rcopy());
     if (!hipok(hipGetLastError())) return GS_ERR_HIP;
@@ -366,17 +387,25 @@ int solve_impl(const Plan& P, const cx<double>* y, cx<double>* x, const gs_solve
         hipLaunchKernelGGL((zero_kernel<double>), dim3(nb256(nx)), dim3(256), 0, st, x, nx);
     }
     if (!hipok(cgls_start<T>(P, st, 0, hist, hist_len))) return GS_ERR_HIP;
+    return GS_OK;
+}
 
-    bool done = false, broke = false;
-    int used = 0, restarts = 0;
-    double rel = -1, rel64 = -1;
-    if (!hipok(cgls_run<T>(P, x, st, opt.max_iter, std::max(1, opt.check_every), hist, hist_len, done, broke)))
-        return GS_ERR_HIP;
-    used = (int)P.host_scal[S_ITER];
-    rel = P.host_scal[S_REF] > 0 ? std::sqrt(P.host_scal[S_GAMMA]) / P.host_scal[S_REF] : 0.0;
-
+// after the recurrence stopped: the FP64 refinement (mixed form), history and info
+template <class T>
+int solve_finish(const Plan& P, cx<double>* x, const gs_solve_opts& opt, gs_solve_info& info, hipStream_t st,
+                 bool done, bool broke) {
+    const int64_t nx = P.dim == 2 ? (int64_t)P.N * P.N : P.N;
+    const int64_t M = P.M;
+    Ops<T> o{P};
+    auto hipok = [&](hipError_t e) { return e == hipSuccess; };
+    const int hist_len = std::min(P.hist_len, opt.history_len);
+    int used = (int)P.host_scal[S_ITER], restarts = 0;
+    double rel = P.host_scal[S_REF] > 0 ? std::sqrt(P.host_scal[S_GAMMA]) / P.host_scal[S_REF] : 0.0;
+    double rel64 = -1;
     const bool refine = opt.refine_fp64 && std::is_same<T, float>::value && P.d64.present;
-    if (refine && !broke) {
+    // mixed form: a stop of the FP32 recurrence (stall or breakdown) is not
+    // final; the FP64 residual decides, and restarts resume from x
+    if (refine) {
         // FP64 reference ||A^H b|| and recomputed FP64 residual
         if (!hipok(launch_apply_TH<double>(P, P.b, P.ss, AFLAGS, st))) return GS_ERR_HIP;
         hipLaunchKernelGGL((norm2_partial_kernel<double>), dim3(RB), dim3(RT), 0, st, P.ss, nx, P.red);
@@ -405,9 +434,9 @@ int solve_impl(const Plan& P, const cx<double>* y, cx<double>* x, const gs_solve
                 return GS_ERR_HIP;
             used += (int)P.host_scal[S_ITER];
             rel = P.host_scal[S_REF] > 0 ? std::sqrt(P.host_scal[S_GAMMA]) / P.host_scal[S_REF] : 0.0;
-            if (broke) break;
         }
         done = rel64 <= opt.rel_tol;
+        broke = !std::isfinite(rel64);
     }
     if (opt.history && hist_len > 0) {
         const int n = std::min(hist_len, used + 1);
@@ -423,6 +452,236 @@ int solve_impl(const Plan& P, const cx<double>* y, cx<double>* x, const gs_solve
     return info.status;
 }
 
+template <class T>
+int solve_impl(const Plan& P, const cx<double>* y, cx<double>* x, const gs_solve_opts& opt, gs_solve_info& info,
+               hipStream_t st) {
+    double* hist = opt.history ? P.hist : nullptr;
+    const int hist_len = std::min(P.hist_len, opt.history_len);
+    int rc = solve_setup<T>(P, y, x, opt, st);
+    if (rc != GS_OK) return rc;
+    bool done = false, broke = false;
+    if (cgls_run<T>(P, x, st, opt.max_iter, std::max(1, opt.check_every), hist, hist_len, done, broke) != hipSuccess)
+        return GS_ERR_HIP;
+    return solve_finish<T>(P, x, opt, info, st, done, broke);
+}
+
+// ------------------------------------------------------------------ batched solve
+//
+// Many independent problems (each with its own plan) advance together.  The
+// CGLS iteration of every problem is captured once as a HIP graph; each round
+// launches the graphs of the problems still running, spread over several
+// streams, and every `check_every` rounds the host reads all stop flags
+// (one synchronization for the whole batch) and drops the problems that are
+// done.  The update kernels also test the device flag, so a round that runs
+// past convergence changes nothing.  Problems go to streams heaviest first
+// (greedy on the point count).  With n_streams = 0 a short trial picks the
+// stream count: each candidate runs a few rounds of the real iteration and the
+// fastest is kept.
+
+struct BatchItem {
+    const Plan* P;
+    cx<double>* x;
+    bool fp32;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int stream = 0;
+    bool active = true, done = false, broke = false;
+};
+
+static hipError_t capture_iteration(BatchItem& it, const gs_solve_opts& opt, hipStream_t cs) {
+    const Plan& P = *it.P;
+    double* hist = opt.history ? P.hist : nullptr;
+    const int hist_len = std::min(P.hist_len, opt.history_len);
+    // per-kernel timing events are host-side records: none inside a graph
+    const bool prof = g_prof_enabled;
+    g_prof_enabled = false;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        g_prof_enabled = prof;
+        return e;
+    }
+    e = it.fp32 ? cgls_iteration<float>(P, it.x, cs, hist, hist_len)
+                : cgls_iteration<double>(P, it.x, cs, hist, hist_len);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    g_prof_enabled = prof;
+    if (e != hipSuccess) return e;
+    if (e2 != hipSuccess) return e2;
+    it.graph = g;
+    return hipGraphInstantiate(&it.exec, g, nullptr, nullptr, 0);
+}
+
+static void assign_streams(std::vector<BatchItem>& items, int ns) {
+    std::vector<int> order(items.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return items[a].P->M > items[b].P->M; });
+    std::vector<double> load(ns, 0.0);
+    for (int i : order) {
+        int s = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        items[i].stream = s;
+        load[s] += (double)items[i].P->M + 4.0 * items[i].P->ng * items[i].P->ng;
+    }
+}
+
+}  // namespace gs
+
+extern "C" int gs_solve_batch(const gs_plan_t* const* plans, int count, const void* const* y, void* const* x,
+                              const gs_solve_opts* opts, gs_solve_info* infos, int n_streams, void* stream) {
+    using namespace gs;
+    if (!plans || count < 1 || !y || !x || !opts || !infos) return GS_ERR_INVALID_ARG;
+    if (!(opts->rel_tol >= 0) || opts->max_iter < 1 || opts->max_restarts < 0) return GS_ERR_INVALID_ARG;
+    if (opts->history) return GS_ERR_INVALID_ARG;  // one host history buffer cannot serve several problems
+    if (n_streams < 0 || n_streams > 64) return GS_ERR_INVALID_ARG;
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i] || !y[i] || !x[i]) return GS_ERR_INVALID_ARG;
+        // each problem owns its plan's work vectors and its own solution
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i] || x[j] == x[i]) return GS_ERR_INVALID_ARG;
+    }
+    const int max_streams = std::min(8, count);
+    hipStream_t user = (hipStream_t)stream;
+    std::vector<BatchItem> items(count);
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> evs;
+    int rc = GS_OK;
+    auto cleanup = [&]() {
+        for (auto& it : items) {
+            if (it.exec) (void)hipGraphExecDestroy(it.exec);
+            if (it.graph) (void)hipGraphDestroy(it.graph);
+        }
+        for (auto e : evs) (void)hipEventDestroy(e);
+        for (auto s : streams) (void)hipStreamDestroy(s);
+    };
+    auto fail = [&](hipError_t e) {
+        (void)e;
+        for (auto s : streams) (void)hipStreamSynchronize(s);
+        cleanup();
+        return GS_ERR_HIP;
+    };
+    const int ns_max = n_streams > 0 ? std::min(n_streams, count) : max_streams;
+    for (int s = 0; s < ns_max; ++s) {
+        hipStream_t h;
+        if (hipStreamCreateWithFlags(&h, hipStreamNonBlocking) != hipSuccess) return fail(hipErrorUnknown);
+        streams.push_back(h);
+    }
+    hipEvent_t ev0;
+    if (hipEventCreateWithFlags(&ev0, hipEventDisableTiming) != hipSuccess) return fail(hipErrorUnknown);
+    evs.push_back(ev0);
+    if (hipEventRecord(ev0, user) != hipSuccess) return fail(hipErrorUnknown);
+    for (auto s : streams)
+        if (hipStreamWaitEvent(s, ev0, 0) != hipSuccess) return fail(hipErrorUnknown);
+
+    for (int i = 0; i < count; ++i) {
+        const Plan& P = plans[i]->impl;
+        items[i].P = &P;
+        items[i].x = (cx<double>*)x[i];
+        items[i].fp32 = P.d32.present && P.precision != GS_F64;
+        infos[i] = gs_solve_info{0, 0, GS_OK, -1.0, -1.0};
+    }
+    assign_streams(items, ns_max);
+    // set-up of every problem, then one captured iteration graph each
+    for (auto& it : items) {
+        hipStream_t s = streams[it.stream];
+        const cx<double>* yi = (const cx<double>*)y[&it - items.data()];
+        rc = it.fp32 ? solve_setup<float>(*it.P, yi, it.x, *opts, s) : solve_setup<double>(*it.P, yi, it.x, *opts, s);
+        if (rc != GS_OK) {
+            for (auto st : streams) (void)hipStreamSynchronize(st);
+            cleanup();
+            return rc;
+        }
+    }
+    for (auto& it : items) {
+        hipError_t e = capture_iteration(it, *opts, streams[it.stream]);
+        if (e != hipSuccess) return fail(e);
+    }
+    const int check_every = std::max(1, opts->check_every);
+    int ns = ns_max;
+    int rounds = 0;
+    // one round: every active problem advances by one iteration
+    auto run_rounds = [&](int n) -> hipError_t {
+        for (int r = 0; r < n; ++r)
+            for (auto& it : items)
+                if (it.active) GS_HIP_TRY(hipGraphLaunch(it.exec, streams[it.stream]));
+        return hipSuccess;
+    };
+    auto check = [&]() -> hipError_t {
+        for (auto& it : items)
+            if (it.active)
+                GS_HIP_TRY(hipMemcpyAsync(it.P->host_scal, it.P->scal, S_NSCAL * sizeof(double),
+                                          hipMemcpyDeviceToHost, streams[it.stream]));
+        for (int s = 0; s < ns; ++s) GS_HIP_TRY(hipStreamSynchronize(streams[s]));
+        for (auto& it : items) {
+            if (!it.active) continue;
+            const double* h = it.P->host_scal;
+            if (h[S_BREAK] != 0.0) {
+                it.broke = true;
+                it.active = false;
+            } else if (h[S_DONE] != 0.0) {
+                it.done = true;
+                it.active = false;
+            } else if ((int)h[S_ITER] >= opts->max_iter) {
+                it.active = false;
+            }
+        }
+        return hipSuccess;
+    };
+    auto any_active = [&]() {
+        for (auto& it : items)
+            if (it.active) return true;
+        return false;
+    };
+    if (n_streams == 0 && ns_max > 1) {
+        // trial: candidate stream counts, a few real rounds each
+        const int trial = std::min(3, opts->max_iter);
+        double best = 1e300;
+        int best_ns = ns_max;
+        for (int cand = 1; cand <= ns_max && rounds + trial <= opts->max_iter && any_active(); cand *= 2) {
+            ns = cand;
+            for (int s = 0; s < ns_max; ++s)
+                if (hipStreamSynchronize(streams[s]) != hipSuccess) return fail(hipErrorUnknown);
+            assign_streams(items, ns);
+            const auto t0 = std::chrono::steady_clock::now();
+            if (run_rounds(trial) != hipSuccess) return fail(hipErrorUnknown);
+            for (int s = 0; s < ns; ++s)
+                if (hipStreamSynchronize(streams[s]) != hipSuccess) return fail(hipErrorUnknown);
+            const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            rounds += trial;
+            if (dt < best) {
+                best = dt;
+                best_ns = cand;
+            }
+            if (check() != hipSuccess) return fail(hipErrorUnknown);
+        }
+        ns = best_ns;
+        assign_streams(items, ns);  // every stream is idle after the last check
+    }
+    while (any_active() && rounds < opts->max_iter) {
+        const int n = std::min(check_every, opts->max_iter - rounds);
+        if (run_rounds(n) != hipSuccess) return fail(hipErrorUnknown);
+        rounds += n;
+        if (check() != hipSuccess) return fail(hipErrorUnknown);
+    }
+    for (int s = 0; s < ns_max; ++s)
+        if (hipStreamSynchronize(streams[s]) != hipSuccess) return fail(hipErrorUnknown);
+    // refinement (mixed form) and results, one problem after the other on the caller's stream
+    int worst = GS_OK;
+    for (int i = 0; i < count; ++i) {
+        BatchItem& it = items[i];
+        if (hipMemcpy(it.P->host_scal, it.P->scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(hipErrorUnknown);
+        int r = it.fp32 ? solve_finish<float>(*it.P, it.x, *opts, infos[i], user, it.done, it.broke)
+                        : solve_finish<double>(*it.P, it.x, *opts, infos[i], user, it.done, it.broke);
+        if (r < 0) {
+            cleanup();
+            return r;
+        }
+        if (r == GS_NOT_CONVERGED && worst == GS_OK) worst = r;
+    }
+    cleanup();
+    return worst;
+}
+
+namespace gs {
 }  // namespace gs
 
 extern "C" int gs_solve(const gs_plan_t* plan, const void* y, void* x, const gs_solve_opts* opts,

@@ -29,7 +29,7 @@ GS_F64, GS_F32, GS_F32_MIXED = 0, 1, 2
 GS_WEIGHTED, GS_SORTED, GS_APPLY_F64 = 1, 2, 4
 
 EXPORTS = [
-    "gs_plan", "gs_apply_T", "gs_apply_TH", "gs_solve", "gs_destroy", "gs_get_plan_info",
+    "gs_plan", "gs_apply_T", "gs_apply_TH", "gs_solve", "gs_solve_batch", "gs_destroy", "gs_get_plan_info",
     "gs_get_permutation", "gs_strerror", "gs_version", "gs_filter_taps", "gs_boundary_filters",
     "gs_eval_basis_1d", "gs_profile_enable", "gs_profile_read",
 ]
@@ -71,6 +71,8 @@ def _load():
     lib.gs_apply_T.argtypes = [vp, vp, vp, i32, vp]
     lib.gs_apply_TH.argtypes = [vp, vp, vp, i32, vp]
     lib.gs_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
+    lib.gs_solve_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                   ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), i32, vp]
     lib.gs_destroy.argtypes = [vp]
     lib.gs_destroy.restype = None
     lib.gs_get_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
@@ -295,6 +297,35 @@ def gs_apply_TH(plan: Plan, u, x=None, **kw):
 
 def gs_solve(plan: Plan, y, x=None, **kw):
     return plan.solve(y, x, **kw)
+
+
+def gs_solve_batch(plans, ys, xs=None, rel_tol=1e-6, max_iter=500, refine_fp64=True, max_restarts=2,
+                   check_every=1, n_streams=0, stream=None):
+    """Solves len(plans) independent problems together (graph-captured CGLS
+    iterations over several streams).  ys[i]: contiguous complex128 of length
+    plans[i].M; xs[i] (optional): complex128 coefficient arrays, zero-started.
+    Returns (xs, list of per-problem result dicts)."""
+    import torch
+    n = len(plans)
+    if n < 1 or len(ys) != n:
+        raise ValueError("need one y per plan")
+    for p, y in zip(plans, ys):
+        if y.dtype != torch.complex128 or not y.is_contiguous() or y.numel() != p.M:
+            raise ValueError("each y must be a contiguous complex128 tensor of length M")
+    if xs is None:
+        xs = [torch.zeros(p.coef_shape(), dtype=torch.complex128, device=y.device) for p, y in zip(plans, ys)]
+    vp = ctypes.c_void_p
+    hp = (vp * n)(*[p.handle for p in plans])
+    yp = (vp * n)(*[y.data_ptr() for y in ys])
+    xp = (vp * n)(*[x.data_ptr() for x in xs])
+    o = SolveOpts(rel_tol, max_iter, 0, int(refine_fp64), max_restarts, check_every, None, 0)
+    infos = (SolveInfo * n)()
+    rc = _lib.gs_solve_batch(hp, n, yp, xp, ctypes.byref(o), infos, n_streams, _stream(stream))
+    if rc < 0:
+        raise GSError(rc, "gs_solve_batch")
+    res = [{"status": i.status, "iterations": i.iterations, "restarts": i.restarts,
+            "rel_residual": i.rel_residual, "rel_residual_fp64": i.rel_residual_fp64} for i in infos]
+    return xs, res
 
 
 def gs_destroy(plan: Plan):

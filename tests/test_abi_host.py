@@ -111,6 +111,28 @@ def test_apply_and_solve_reject_null_arguments():
     lib.gs_destroy(None)      # ignored
 
 
+def test_solve_batch_rejects_bad_arguments():
+    """Argument checks happen before any device work (no GPU needed)."""
+    lib = gs.library()
+    vp = ctypes.c_void_p
+    opts = gs.SolveOpts(1e-6, 10, 0, 1, 2, 1, None, 0)
+    infos = (gs.SolveInfo * 2)()
+    one = (vp * 2)(16, 32)
+    null2 = (vp * 2)(None, None)
+    assert lib.gs_solve_batch(None, 1, one, one, ctypes.byref(opts), infos, 0, None) == gs.GS_ERR_INVALID_ARG
+    assert lib.gs_solve_batch(one, 0, one, one, ctypes.byref(opts), infos, 0, None) == gs.GS_ERR_INVALID_ARG
+    assert lib.gs_solve_batch(null2, 2, one, one, ctypes.byref(opts), infos, 0, None) == gs.GS_ERR_INVALID_ARG
+    assert lib.gs_solve_batch(one, 2, one, one, None, infos, 0, None) == gs.GS_ERR_INVALID_ARG
+    assert lib.gs_solve_batch(one, 2, one, one, ctypes.byref(opts), infos, -1, None) == gs.GS_ERR_INVALID_ARG
+    # the same plan twice, or a shared solution buffer
+    same = (vp * 2)(16, 16)
+    assert lib.gs_solve_batch(same, 2, one, one, ctypes.byref(opts), infos, 0, None) == gs.GS_ERR_INVALID_ARG
+    assert lib.gs_solve_batch(one, 2, one, same, ctypes.byref(opts), infos, 0, None) == gs.GS_ERR_INVALID_ARG
+    hist = (ctypes.c_double * 4)()
+    opts_h = gs.SolveOpts(1e-6, 10, 0, 1, 2, 1, hist, 4)
+    assert lib.gs_solve_batch(one, 2, one, one, ctypes.byref(opts_h), infos, 0, None) == gs.GS_ERR_INVALID_ARG
+
+
 def test_eval_basis_rejects_bad_input():
     with pytest.raises(gs.GSError):
         gs.gs_eval_basis_1d(6, 2, np.array([0.0, np.nan]))

@@ -1,0 +1,137 @@
+"""Batched CGLS (gs_solve_batch) on uneven 2D problems.
+
+Every problem in a batch runs the same kernels in the same order as a lone
+gs_solve on its plan, so its iterate, iteration count, restarts and recurred
+residual must equal the lone solve's bit for bit, whatever the stream count
+and check interval.  A well-conditioned member is also held to the oracle's
+least-squares solution (within 1e-6), like the single-problem solve."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import basis, lsq
+from workloads import (complex_noise, config_c4_problem, ellipse_phantom_params, jitter_2d,
+                       phantom_cell_averages, spiral_2d, voronoi_weights_2d)
+
+from gpu_util import crandn, rel, to_dev, to_host, say
+
+pytestmark = pytest.mark.gpu
+
+# (J, p, pattern, precision): uneven sizes, both wavelet orders, both patterns,
+# FP64 and FP32-mixed plans in one batch
+SPECS = [(5, 4, "jitter", 0), (6, 2, "spiral", 2), (4, 2, "jitter", 2), (7, 4, "spiral", 2),
+         (6, 4, "jitter", 0), (5, 2, "spiral", 2), (3, 4, "jitter", 2)]
+
+
+def _pattern(J, pat, seed):
+    """Well-conditioned patterns (a jittered grid over [-N, N]^2, a spiral of
+    radius 0.75 N) with Voronoi weights."""
+    N = 1 << J
+    if pat == "jitter":
+        pts = jitter_2d(4 * N * N, N, seed)
+        mu = voronoi_weights_2d(pts, "square", N, 1.0)
+    else:
+        pts = spiral_2d(64, max(8, 140 * N // 32), 0.75 * N, 0.5)
+        mu = voronoi_weights_2d(pts, "disk", 0.75 * N + 0.25, 0.4)
+    return pts, mu
+
+
+@pytest.fixture(scope="module")
+def batch():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1607_04091_amd import gs
+    plans, ys, data = [], [], []
+    for k, (J, p, pat, prec) in enumerate(SPECS):
+        pts, mu = _pattern(J, pat, 600 + k)
+        plans.append(gs.gs_plan(2, J, p, pts, mu, precision=prec))
+        if k == 0:
+            # member 0: data from the oracle's T and a phantom, plus noise
+            x0 = phantom_cell_averages(ellipse_phantom_params(601), J).astype(complex)
+            T = basis.dense_T_2d(pts, J, p)
+            y = T @ x0.reshape(-1)
+            y = y + complex_noise(y.size, 1e-4 * np.linalg.norm(y) / np.sqrt(2 * y.size), 602)
+            data.append((T, y, mu))
+        else:
+            y = crandn(np.random.default_rng(610 + k), pts.shape[0])
+        ys.append(to_dev(y, torch.complex128))
+    yield gs, plans, ys, data
+    for pl in plans:
+        pl.destroy()
+
+
+def _lone(gs, plans, ys, **kw):
+    out = []
+    for pl, y in zip(plans, ys):
+        x, info = pl.solve(y, rel_tol=kw.get("rel_tol", 1e-6), max_iter=kw.get("max_iter", 400),
+                           refine_fp64=True, max_restarts=3, check_every=1)
+        out.append((to_host(x), info))
+    return out
+
+
+def _same(batched, lone):
+    xs, infos = batched
+    for i, ((x1, i1), x2, i2) in enumerate(zip(lone, xs, infos)):
+        x2 = to_host(x2)
+        for key in ("status", "iterations", "restarts", "rel_residual", "rel_residual_fp64"):
+            assert i1[key] == i2[key], (i, key, i1[key], i2[key])
+        assert np.array_equal(x1, x2), (i, rel(x2, x1))
+
+
+@pytest.mark.parametrize("n_streams,check_every", [(0, 1), (3, 4), (1, 7)])
+def test_batch_equals_lone_solves(batch, n_streams, check_every):
+    gs, plans, ys, _ = batch
+    say(f"[batch] {len(plans)} problems, n_streams={n_streams} check_every={check_every}")
+    lone = _lone(gs, plans, ys)
+    got = gs.gs_solve_batch(plans, ys, rel_tol=1e-6, max_iter=400, refine_fp64=True, max_restarts=3,
+                            check_every=check_every, n_streams=n_streams)
+    # member 3 (a spiral at J = 7) is ill-conditioned and stops at max_iter
+    st = [r["status"] for r in got[1]]
+    assert all(s == gs.GS_OK for i, s in enumerate(st) if i != 3), st
+    _same(got, lone)
+
+
+def test_batch_budget_exhausted(batch):
+    """max_iter too small for any problem: every status is GS_NOT_CONVERGED,
+    and the iterates still equal the lone solves'."""
+    gs, plans, ys, _ = batch
+    say("[batch] max_iter=7")
+    lone = _lone(gs, plans, ys, max_iter=7)
+    got = gs.gs_solve_batch(plans, ys, rel_tol=1e-6, max_iter=7, refine_fp64=True, max_restarts=3,
+                            check_every=2, n_streams=0)
+    assert all(r["status"] == gs.GS_NOT_CONVERGED for r in got[1])
+    _same(got, lone)
+
+
+def test_batch_member_matches_lstsq(batch):
+    gs, plans, ys, data = batch
+    say("[batch] member 0 against the oracle LS solution")
+    T, y, mu = data[0]
+    N = 1 << SPECS[0][0]
+    x_ref = lsq.lstsq_dense(T, y, mu).reshape(N, N)
+    xs, infos = gs.gs_solve_batch(plans, ys, rel_tol=1e-10, max_iter=400, refine_fp64=True, max_restarts=3,
+                                  check_every=5, n_streams=2)
+    assert infos[0]["status"] == gs.GS_OK
+    assert rel(to_host(xs[0]), x_ref) < 1e-6
+
+
+def test_batch_first_c4_problems():
+    """The first eight problems of the 64-problem workload (J 6..9, up to
+    863,041 points, FP32-mixed plans, constant area weights): batched equals
+    lone."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1607_04091_amd import gs
+    plans, ys = [], []
+    for b in range(8):
+        c = config_c4_problem(b, "area")
+        plans.append(gs.gs_plan(2, c["J"], c["p"], c["xi"], c["mu"], precision=gs.GS_F32_MIXED))
+        ys.append(to_dev(crandn(np.random.default_rng(4300 + b), c["xi"].shape[0]), torch.complex128))
+    say(f"[batch c4x8] M={[pl.M for pl in plans]}")
+    lone = _lone(gs, plans, ys, rel_tol=1e-6, max_iter=60)
+    got = gs.gs_solve_batch(plans, ys, rel_tol=1e-6, max_iter=60, refine_fp64=True, max_restarts=3,
+                            check_every=10, n_streams=0)
+    _same(got, lone)
+    for pl in plans:
+        pl.destroy()

@@ -112,3 +112,35 @@ def test_warm_start_and_limits(gs):
     assert ia["iterations"] == info_cold["iterations"]
     assert torch.equal(xa, x_cold)
     plan.destroy()
+
+
+@pytest.mark.parametrize("J,p,pattern", [(4, 2, "jitter"), (5, 2, "spiral")])
+def test_mixed_below_fp32_floor_is_graceful(gs, J, p, pattern):
+    """An inconsistent problem (random data) asked for a tolerance below what
+    FP32 applies can reach: the FP32 recurrence stalls, the FP64 residual is
+    recomputed and the recurrence restarted; the result is GS_OK or
+    GS_NOT_CONVERGED with a finite iterate whose FP64 normal residual is small,
+    never a breakdown."""
+    say(f"[mixed floor] J={J} p={p} {pattern}")
+    N = 1 << J
+    pts, mu, _ = _small_2d(J, p, pattern)
+    y = crandn(np.random.default_rng(77), pts.shape[0])
+    plan = gs.gs_plan(2, J, p, pts, mu, precision=gs.GS_F32_MIXED)
+    x, info = plan.solve(to_dev(y, torch.complex128), rel_tol=1e-9, max_iter=400, refine_fp64=True,
+                         max_restarts=3)
+    xh = to_host(x)
+    say(f"  status={info['status']} iters={info['iterations']} restarts={info['restarts']} "
+        f"rr64={info['rel_residual_fp64']:.2e}")
+    assert info["status"] in (gs.GS_OK, gs.GS_NOT_CONVERGED)
+    assert np.isfinite(xh).all()
+    assert 0 <= info["rel_residual_fp64"] < 1e-4
+    # its weighted LS objective is that of the oracle's LS solution, to 1e-6
+    T = basis.dense_T_2d(pts, J, p)
+    x_ref = lsq.lstsq_dense(T, y, mu)
+    w = np.sqrt(mu)
+
+    def objective(v):
+        return np.linalg.norm(w * (T @ v - y))
+
+    assert objective(xh.reshape(-1)) <= objective(x_ref) * (1 + 1e-6)
+    plan.destroy()

@@ -77,21 +77,36 @@ def config_c3(J: int = 9, arms: int = 64, per_arm: int = 16384, r_max: float = 2
     }
 
 
-def config_c4_problem(b: int, with_weights: bool = True):
-    """Problem b (0..63) of the batched workload, seed 4000 + b."""
+def config_c4_problem(b: int, weights: str = "voronoi"):
+    """Problem b (0..63) of the batched workload, seed 4000 + b.
+
+    weights: "voronoi" (cell areas, as C3), "area" (the mean area per point,
+    constant: h^2 for the jittered grid, arm gap times arc spacing for the
+    spiral -- an O(1) stand-in for the Voronoi areas, which cost tens of
+    seconds per million points) or "none"."""
     rng = np.random.default_rng(4000 + b)
     p = int(rng.choice([2, 4]))
     J = int(rng.integers(6, 10))
     pattern = "jitter" if rng.integers(0, 2) == 0 else "spiral"
     M = int(round(rng.uniform(2, 4) * 4 ** J))
     half = 2.0 ** (J - 1)
+    if weights not in ("voronoi", "area", "none"):
+        raise ValueError(weights)
     if pattern == "jitter":
         pts = jitter_2d(M, half, 4100 + b)
-        mu = voronoi_weights_2d(pts, "square", half, 2 * half / math.sqrt(M)) if with_weights else None
+        s = int(round(math.sqrt(M)))
+        if weights == "voronoi":
+            mu = voronoi_weights_2d(pts, "square", half, 2 * half / math.sqrt(M))
+        else:
+            mu = np.full(pts.shape[0], (2 * half / s) ** 2) if weights == "area" else None
     else:
         per_arm = max(1, M // 64)
         pts = spiral_2d(64, per_arm, half, 0.5)
-        mu = voronoi_weights_2d(pts, "disk", half + 0.25, 0.4) if with_weights else None
+        if weights == "voronoi":
+            mu = voronoi_weights_2d(pts, "disk", half + 0.25, 0.4)
+        else:
+            # disk area over the point count = arm gap x arc spacing on average
+            mu = np.full(pts.shape[0], math.pi * half * half / pts.shape[0]) if weights == "area" else None
     x0 = phantom_cell_averages(ellipse_phantom_params(4200 + b), J).astype(np.complex128)
     return {"name": f"c4_{b}", "dim": 2, "J": J, "p": p, "pattern": pattern,
             "xi": pts, "mu": mu, "x0": x0, "tol": 1e-6}
