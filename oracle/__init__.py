@@ -23,4 +23,7 @@ Every function is a plain, slow, obviously-correct restatement of the paper:
                      by a library QR/SVD solver and by CGLS.
 * ``cascade``     -- scaling functions in space on dyadic grids; used only to
                      pin the Fourier-side routines independently.
+* ``cnn``         -- the learned warm start (not from the paper): 3x3
+                     convolutions, the residual network, its loss, backward
+                     pass and Adam, with optional bf16 storage rounding.
 """
