@@ -61,6 +61,8 @@ extern "C" {
 /* apply flags */
 #define GS_WEIGHTED  1   /* apply W^{1/2} T (resp. T^H W^{1/2}) instead of T (T^H)      */
 #define GS_SORTED    2   /* sample vectors are in the plan's internal point order       */
+#define GS_WEIGHT_FULL 8 /* with GS_WEIGHTED: W T (T^H W) instead of W^{1/2} T (T^H W^{1/2});
+                            T^H W y is A^H b, the warm-start network's input            */
 #define GS_APPLY_F64 4   /* on a GS_F32_MIXED plan: run the FP64 apply (complex128 IO)  */
 
 typedef struct gs_plan gs_plan_t;
@@ -108,7 +110,8 @@ int gs_apply_TH(const gs_plan_t* plan, const void* u, void* x, int flags, void* 
 typedef struct gs_solve_opts {
     double rel_tol;        /* stop when ||A^H(b - A x)|| <= rel_tol ||A^H b||, A = W^{1/2}T */
     int    max_iter;       /* >= 1                                                        */
-    int    warm_start;     /* nonzero: x holds x0 on entry; else x0 = 0                  */
+    int    warm_start;     /* 0: x0 = 0; 1: x holds x0 on entry; 2: guarded -- x0 is
+                              kept only if ||A^H(b - A x0)|| < ||A^H b||, else x0 = 0     */
     int    refine_fp64;    /* GS_F32_MIXED plans: FP64 residual refinement at the end    */
     int    max_restarts;   /* refinement restarts allowed (mixed form), >= 0             */
     int    check_every;    /* iterations between host reads of the stop flag (>= 1)      */
@@ -122,6 +125,7 @@ typedef struct gs_solve_info {
     int    status;              /* GS_OK, GS_NOT_CONVERGED or GS_ERR_BREAKDOWN          */
     double rel_residual;        /* final relative normal residual (recurred)           */
     double rel_residual_fp64;   /* recomputed with FP64 applies (mixed form), else -1  */
+    int    warm_start_used;     /* 1 if the iteration started from the caller's x0     */
 } gs_solve_info;
 
 /*
@@ -221,6 +225,67 @@ int gs_boundary_filters(int p, double* U_left, double* V_left, double* v0_left,
  * (Sec. 4 entries of T; an interior column n is D * exp(-2 pi i (n-N/2) 2^-J xi).)
  */
 int gs_eval_basis_1d(int J, int p, int64_t M, const double* xi, double* out);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start (not from the paper, which starts CGLS from zero).
+ * A residual CNN maps the adjoint image A^H b = T^H W y of a 2D problem to an
+ * estimate of the LS solution, used as gs_solve's x0 (opts.warm_start).
+ *
+ * Network: u = s * input (fixed scale s); conv3x3 2->32 + ReLU,
+ * 4 x (conv3x3 32->32 + ReLU), conv3x3 32->2; output = u + last conv.  Convolutions are cross-correlations with zero
+ * padding, no biases; weights w[ky][kx][ci][co].  Images are (batch, H, W)
+ * complex arrays (channels re, im), H x W = N x N coefficients, row-major as
+ * gs_solve's x.  Activations and hidden-layer gradients are stored in
+ * bfloat16, products use bf16 copies of FP32 master weights, sums are FP32;
+ * the 32->32 layers run on MFMA.  Loss: sum ||out - t||^2 / sum ||t||^2 over
+ * the batch.  Optimizer: Adam.  Deterministic (no atomics).
+ *
+ * Parameters, as one FP32 host array of gs_cnn_param_count() = 38016 values:
+ * layers 1..6 in order, each w[ky][kx][ci][co] row-major.
+ * One handle serves one stream at a time.
+ * ------------------------------------------------------------------------ */
+typedef struct gs_cnn gs_cnn_t;
+
+#define GS_CNN_IN_F64   1   /* forward input is complex128 (else complex64)               */
+#define GS_CNN_OUT_F64  2   /* forward output is complex128 (else complex64)              */
+#define GS_CNN_TRAIN    4   /* keep what gs_cnn_backward needs; out may then be NULL      */
+#define GS_CNN_TGT_F64  8   /* backward target is complex128 (else complex64)             */
+
+int gs_cnn_param_count(void);
+
+/* Fixed (untrained) input scale s > 0: the network sees s * input and its
+ * output is s * input + last conv.  It brings A^H b to the size of x.
+ * Default 1. */
+int gs_cnn_set_input_scale(gs_cnn_t* cnn, float scale);
+int gs_cnn_get_input_scale(const gs_cnn_t* cnn, float* scale);
+
+/* Allocates a network for images of height x width and batches up to
+ * max_batch (device memory ~ 7 x 64 B per pixel of the largest batch).
+ * Weights start at zero: set them with gs_cnn_set_weights. */
+int gs_cnn_create(gs_cnn_t** out, int height, int width, int max_batch);
+void gs_cnn_destroy(gs_cnn_t* cnn);
+
+/* Host FP32 parameter arrays (38016 values).  set_weights also clears the
+ * Adam moments and step count; it rejects non-finite values. */
+int gs_cnn_set_weights(gs_cnn_t* cnn, const float* host_params);
+int gs_cnn_get_weights(const gs_cnn_t* cnn, float* host_params);
+int gs_cnn_get_grads(const gs_cnn_t* cnn, float* host_params);   /* of the last backward */
+/* Adam state (checkpoint / resume): first and second moments, step count. */
+int gs_cnn_get_state(const gs_cnn_t* cnn, float* m, float* v, int* step);
+int gs_cnn_set_state(gs_cnn_t* cnn, const float* m, const float* v, int step);
+
+/* in: device, batch x H x W complex; out: device, same shape (may be NULL
+ * with GS_CNN_TRAIN).  Asynchronous on `stream`. */
+int gs_cnn_forward(gs_cnn_t* cnn, const void* in, void* out, int batch, int flags, void* stream);
+
+/* Loss and parameter gradients for the preceding GS_CNN_TRAIN forward of the
+ * same batch (else GS_ERR_INVALID_ARG).  target: device, batch x H x W complex.
+ * If loss != NULL, synchronizes `stream` and stores the loss there. */
+int gs_cnn_backward(gs_cnn_t* cnn, const void* target, int batch, int flags, double* loss, void* stream);
+
+/* One Adam step on the gradients of the last backward (bias-corrected,
+ * step count kept by the handle). */
+int gs_cnn_step(gs_cnn_t* cnn, float lr, float beta1, float beta2, float eps, void* stream);
 
 #ifdef __cplusplus
 }

@@ -13,9 +13,9 @@ definitions so that the GPU kernels have something independent to match:
                        a[b, y+dy, x+dx, ci] * w[dy+1, dx+1, ci, co],
   a taken as 0 outside the image.  No biases (the map from A^H b to the LS
   solution is linear, and a bias-free ReLU net is positively homogeneous).
-* Network: the complex image u becomes two real channels (re, im);
-  conv 2->C, ReLU; four times conv C->C, ReLU; conv C->2; output
-  = input + last conv (residual form).  C = 32 by default.
+* Network: the complex image u becomes two real channels (re, im),
+  multiplied by a fixed scale s; conv 2->C, ReLU; four times conv C->C,
+  ReLU; conv C->2; output = s u + last conv (residual form).  C = 32.
 * Loss: relative squared error over the batch,
       L = sum_b ||out_b - t_b||^2 / sum_b ||t_b||^2.
 * Backward by the chain rule, written out per layer (no autodiff).
@@ -103,10 +103,11 @@ def to_complex(a):
     return a[..., 0] + 1j * a[..., 1]
 
 
-def forward(weights, u, emulate: bool = True):
-    """Returns (out as (B, H, W, 2), cache).  u: (B, H, W) complex."""
+def forward(weights, u, emulate: bool = True, scale: float = 1.0):
+    """Returns (out as (B, H, W, 2), cache).  u: (B, H, W) complex; the
+    network sees scale * u (FP32: the input rounded to FP32, then scaled)."""
     rnd = bf16_round if emulate else (lambda v: v)
-    a = f32(to_channels(u)) if emulate else to_channels(u)
+    a = f32(f32(to_channels(u)) * f32(scale)) if emulate else scale * to_channels(u)
     acts = [a]
     wq = [rnd(w) for w in weights]
     for l in range(N_LAYERS - 1):

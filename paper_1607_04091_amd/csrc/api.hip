@@ -363,7 +363,8 @@ void gs_destroy(gs_plan_t* plan) {
 
 static int pick_apply(const gs_plan_t* plan, const void* a, const void* b, int flags, bool& use64) {
     if (!plan || !a || !b) return GS_ERR_INVALID_ARG;
-    if (flags & ~(GS_WEIGHTED | GS_SORTED | GS_APPLY_F64)) return GS_ERR_INVALID_ARG;
+    if (flags & ~(GS_WEIGHTED | GS_SORTED | GS_APPLY_F64 | GS_WEIGHT_FULL)) return GS_ERR_INVALID_ARG;
+    if ((flags & GS_WEIGHT_FULL) && !(flags & GS_WEIGHTED)) return GS_ERR_INVALID_ARG;
     const gs::Plan& P = plan->impl;
     if (P.precision == GS_F64) use64 = true;
     else if (P.precision == GS_F32) {

@@ -362,7 +362,8 @@ hipError_t cgls_run(const Plan& P, cx<double>* x, hipStream_t st, int budget, in
 
 // b, reference ||A^H b||, initial residual (x0 = 0 or warm start), s, gamma, p
 template <class T>
-int solve_setup(const Plan& P, const cx<double>* y, cx<double>* x, const gs_solve_opts& opt, hipStream_t st) {
+int solve_setup(const Plan& P, const cx<double>* y, cx<double>* x, const gs_solve_opts& opt, hipStream_t st,
+                int* warm_used) {
     const int64_t nx = P.dim == 2 ? (int64_t)P.N * P.N : P.N;
     const int64_t M = P.M;
     Ops<T> o{P};
@@ -381,12 +382,28 @@ int solve_setup(const Plan& P, const cx<double>* y, cx<double>* x, const gs_solv
     if (!hipok(launch_apply_TH<T>(P, o.ra(), o.sa(), AFLAGS, st))) return GS_ERR_HIP;
     hipLaunchKernelGGL((norm2_partial_kernel<T>), dim3(RB), dim3(RT), 0, st, o.sa(), nx, P.red);
     hipLaunchKernelGGL(start_scalars_kernel, dim3(1), dim3(RT), 0, st, P.scal, P.red, 1, nullptr, 0);
-    if (opt.warm_start) {
+    bool warm = opt.warm_start != 0;
+    if (warm) {
         if (!hipok(compute_residual<T>(P, x, st))) return GS_ERR_HIP;
     } else {
         hipLaunchKernelGGL((zero_kernel<double>), dim3(nb256(nx)), dim3(256), 0, st, x, nx);
     }
     if (!hipok(cgls_start<T>(P, st, 0, hist, hist_len))) return GS_ERR_HIP;
+    if (warm && opt.warm_start == 2) {
+        // guarded start: keep x0 only if ||A^H(b - A x0)|| < ||A^H b|| (zero start's value)
+        if (!hipok(hipMemcpyAsync(P.host_scal, P.scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, st)) ||
+            !hipok(hipStreamSynchronize(st)))
+            return GS_ERR_HIP;
+        const double g = P.host_scal[S_GAMMA], ref = P.host_scal[S_REF];
+        if (!(g < ref * ref)) {
+            warm = false;
+            hipLaunchKernelGGL((zero_kernel<double>), dim3(nb256(nx)), dim3(256), 0, st, x, nx);
+            hipLaunchKernelGGL((init_b_kernel<T>), dim3(nb256(M)), dim3(256), 0, st, y, P.perm, P.smu64, M, P.b,
+                               P.r, o.rcopy());
+            if (!hipok(cgls_start<T>(P, st, 0, hist, hist_len))) return GS_ERR_HIP;
+        }
+    }
+    if (warm_used) *warm_used = warm ? 1 : 0;
     return GS_OK;
 }
 
@@ -457,8 +474,10 @@ int solve_impl(const Plan& P, const cx<double>* y, cx<double>* x, const gs_solve
                hipStream_t st) {
     double* hist = opt.history ? P.hist : nullptr;
     const int hist_len = std::min(P.hist_len, opt.history_len);
-    int rc = solve_setup<T>(P, y, x, opt, st);
+    int warm_used = 0;
+    int rc = solve_setup<T>(P, y, x, opt, st, &warm_used);
     if (rc != GS_OK) return rc;
+    info.warm_start_used = warm_used;
     bool done = false, broke = false;
     if (cgls_run<T>(P, x, st, opt.max_iter, std::max(1, opt.check_every), hist, hist_len, done, broke) != hipSuccess)
         return GS_ERR_HIP;
@@ -486,6 +505,7 @@ struct BatchItem {
     hipGraphExec_t exec = nullptr;
     int stream = 0;
     bool active = true, done = false, broke = false;
+    int warm_used = 0;
 };
 
 static hipError_t capture_iteration(BatchItem& it, const gs_solve_opts& opt, hipStream_t cs) {
@@ -530,6 +550,7 @@ extern "C" int gs_solve_batch(const gs_plan_t* const* plans, int count, const vo
     using namespace gs;
     if (!plans || count < 1 || !y || !x || !opts || !infos) return GS_ERR_INVALID_ARG;
     if (!(opts->rel_tol >= 0) || opts->max_iter < 1 || opts->max_restarts < 0) return GS_ERR_INVALID_ARG;
+    if (opts->warm_start < 0 || opts->warm_start > 2) return GS_ERR_INVALID_ARG;
     if (opts->history) return GS_ERR_INVALID_ARG;  // one host history buffer cannot serve several problems
     if (n_streams < 0 || n_streams > 64) return GS_ERR_INVALID_ARG;
     for (int i = 0; i < count; ++i) {
@@ -576,14 +597,17 @@ extern "C" int gs_solve_batch(const gs_plan_t* const* plans, int count, const vo
         items[i].P = &P;
         items[i].x = (cx<double>*)x[i];
         items[i].fp32 = P.d32.present && P.precision != GS_F64;
-        infos[i] = gs_solve_info{0, 0, GS_OK, -1.0, -1.0};
+        infos[i] = gs_solve_info{0, 0, GS_OK, -1.0, -1.0, 0};
     }
     assign_streams(items, ns_max);
     // set-up of every problem, then one captured iteration graph each
     for (auto& it : items) {
         hipStream_t s = streams[it.stream];
         const cx<double>* yi = (const cx<double>*)y[&it - items.data()];
-        rc = it.fp32 ? solve_setup<float>(*it.P, yi, it.x, *opts, s) : solve_setup<double>(*it.P, yi, it.x, *opts, s);
+        int wu = 0;
+        rc = it.fp32 ? solve_setup<float>(*it.P, yi, it.x, *opts, s, &wu)
+                     : solve_setup<double>(*it.P, yi, it.x, *opts, s, &wu);
+        it.warm_used = wu;
         if (rc != GS_OK) {
             for (auto st : streams) (void)hipStreamSynchronize(st);
             cleanup();
@@ -671,6 +695,7 @@ extern "C" int gs_solve_batch(const gs_plan_t* const* plans, int count, const vo
             return fail(hipErrorUnknown);
         int r = it.fp32 ? solve_finish<float>(*it.P, it.x, *opts, infos[i], user, it.done, it.broke)
                         : solve_finish<double>(*it.P, it.x, *opts, infos[i], user, it.done, it.broke);
+        infos[i].warm_start_used = it.warm_used;
         if (r < 0) {
             cleanup();
             return r;
@@ -691,10 +716,11 @@ extern "C" int gs_solve(const gs_plan_t* plan, const void* y, void* x, const gs_
                         void* stream) {
     if (!plan || !y || !x || !opts) return GS_ERR_INVALID_ARG;
     if (!(opts->rel_tol >= 0) || opts->max_iter < 1 || opts->max_restarts < 0) return GS_ERR_INVALID_ARG;
+    if (opts->warm_start < 0 || opts->warm_start > 2) return GS_ERR_INVALID_ARG;
     if (opts->history && opts->history_len < 1) return GS_ERR_INVALID_ARG;
     gs_solve_info local{};
     gs_solve_info& inf = info ? *info : local;
-    inf = gs_solve_info{0, 0, GS_OK, -1.0, -1.0};
+    inf = gs_solve_info{0, 0, GS_OK, -1.0, -1.0, 0};
     const gs::Plan& P = plan->impl;
     hipStream_t st = (hipStream_t)stream;
     if (P.d32.present && P.precision != GS_F64)

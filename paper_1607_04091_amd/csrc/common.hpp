@@ -35,6 +35,11 @@ template <class T> __host__ __device__ inline cx<T> cmacc(cx<T> acc, cx<T> a, cx
 }
 template <class T> __host__ __device__ inline cx<T> czero() { return mk<T>(T(0), T(0)); }
 
+// per-point weight factor of a weighted apply: sqrt(mu), or mu with GS_WEIGHT_FULL
+template <class T> __host__ __device__ inline T wscale(T smu, int flags) {
+    return (flags & GS_WEIGHT_FULL) ? smu * smu : smu;
+}
+
 // ------------------------------------------------------------ plan
 // Window / NFFT parameters per precision.
 constexpr int W32 = 8, DEG32 = 7;     // FP32 path: 8 taps, degree-7 polynomial

@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(256) interp2d_kernel(Geo<T> g, const cx<T>* __
             res = cmac(res, cmul(ay[r], Dx), Cc);
         }
     }
-    if (flags & GS_WEIGHTED) res = cscale(res, g.smu[m]);
+    if (flags & GS_WEIGHTED) res = cscale(res, wscale(g.smu[m], flags));
     y[(flags & GS_SORTED) ? m : g.perm[m]] = res;
 }
 
@@ -292,7 +292,7 @@ __global__ void __launch_bounds__(256) interp1d_kernel(Geo<T> g, const cx<T>* __
     cx<T> res = cmul(g.chx[NB * M + m], I);
 #pragma unroll
     for (int r = 0; r < 2 * NB; ++r) res = cmac(res, g.chx[(size_t)g.bchan(r) * M + m], x[g.bcol(r)]);
-    if (flags & GS_WEIGHTED) res = cscale(res, g.smu[m]);
+    if (flags & GS_WEIGHTED) res = cscale(res, wscale(g.smu[m], flags));
     y[(flags & GS_SORTED) ? m : g.perm[m]] = res;
 }
 
@@ -305,7 +305,7 @@ __global__ void adj_prep_kernel(Geo<T> g, const cx<T>* __restrict__ u, cx<T>* __
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= g.M) return;
     cx<T> val = u[(flags & GS_SORTED) ? m : g.perm[m]];
-    if (flags & GS_WEIGHTED) val = cscale(val, g.smu[m]);
+    if (flags & GS_WEIGHTED) val = cscale(val, wscale(g.smu[m], flags));
     v[m] = val;
     const size_t M = g.M;
     cx<T> D = g.chx[(size_t)g.nb * M + m];

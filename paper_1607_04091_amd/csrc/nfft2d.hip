@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(256) interp_tile_kernel(TileGeo<T> g, const cx
         }
         cx<T> res = cmul(cmul(g.chx[nb * M + q], g.chy[nb * M + q]), I);
         if constexpr (BND) res = cadd(res, ybnd[q]);
-        if (flags & GS_WEIGHTED) res = cscale(res, g.smu[q]);
+        if (flags & GS_WEIGHTED) res = cscale(res, wscale(g.smu[q], flags));
         y[(flags & GS_SORTED) ? q : g.perm[q]] = res;
     }
 }
@@ -265,7 +265,7 @@ __global__ void adj_gather_kernel(TileGeo<T> g, const cx<T>* __restrict__ u, int
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= g.M) return;
     cx<T> v = u[(flags & GS_SORTED) ? q : g.perm[q]];
-    if (flags & GS_WEIGHTED) v = cscale(v, g.smu[q]);
+    if (flags & GS_WEIGHTED) v = cscale(v, wscale(g.smu[q], flags));
     vs[q] = v;
 }
 

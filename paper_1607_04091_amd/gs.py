@@ -26,13 +26,25 @@ GS_ERR_BREAKDOWN = -6
 GS_ERR_PRECISION = -7
 
 GS_F64, GS_F32, GS_F32_MIXED = 0, 1, 2
-GS_WEIGHTED, GS_SORTED, GS_APPLY_F64 = 1, 2, 4
+GS_WEIGHTED, GS_SORTED, GS_APPLY_F64, GS_WEIGHT_FULL = 1, 2, 4, 8
+
+
+def _wflags(weighted):
+    """weighted: False, True (W^{1/2}) or "full" (W)."""
+    if weighted == "full":
+        return GS_WEIGHTED | GS_WEIGHT_FULL
+    return GS_WEIGHTED if weighted else 0
 
 EXPORTS = [
     "gs_plan", "gs_apply_T", "gs_apply_TH", "gs_solve", "gs_solve_batch", "gs_destroy", "gs_get_plan_info",
     "gs_get_permutation", "gs_strerror", "gs_version", "gs_filter_taps", "gs_boundary_filters",
     "gs_eval_basis_1d", "gs_profile_enable", "gs_profile_read",
+    "gs_cnn_param_count", "gs_cnn_create", "gs_cnn_destroy", "gs_cnn_set_weights", "gs_cnn_get_weights",
+    "gs_cnn_get_grads", "gs_cnn_get_state", "gs_cnn_set_state", "gs_cnn_forward", "gs_cnn_backward", "gs_cnn_step",
+    "gs_cnn_set_input_scale", "gs_cnn_get_input_scale",
 ]
+
+GS_CNN_IN_F64, GS_CNN_OUT_F64, GS_CNN_TRAIN, GS_CNN_TGT_F64 = 1, 2, 4, 8
 
 
 class GSError(RuntimeError):
@@ -49,7 +61,8 @@ class SolveOpts(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("status", ctypes.c_int),
-                ("rel_residual", ctypes.c_double), ("rel_residual_fp64", ctypes.c_double)]
+                ("rel_residual", ctypes.c_double), ("rel_residual_fp64", ctypes.c_double),
+                ("warm_start_used", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -73,6 +86,21 @@ def _load():
     lib.gs_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
     lib.gs_solve_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                    ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), i32, vp]
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.gs_cnn_param_count.argtypes = []
+    lib.gs_cnn_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32]
+    lib.gs_cnn_destroy.argtypes = [vp]
+    lib.gs_cnn_destroy.restype = None
+    lib.gs_cnn_set_weights.argtypes = [vp, fp]
+    lib.gs_cnn_get_weights.argtypes = [vp, fp]
+    lib.gs_cnn_get_grads.argtypes = [vp, fp]
+    lib.gs_cnn_get_state.argtypes = [vp, fp, fp, ctypes.POINTER(ctypes.c_int)]
+    lib.gs_cnn_set_state.argtypes = [vp, fp, fp, i32]
+    lib.gs_cnn_forward.argtypes = [vp, vp, vp, i32, i32, vp]
+    lib.gs_cnn_backward.argtypes = [vp, vp, i32, i32, dp, vp]
+    lib.gs_cnn_set_input_scale.argtypes = [vp, ctypes.c_float]
+    lib.gs_cnn_get_input_scale.argtypes = [vp, fp]
+    lib.gs_cnn_step.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
     lib.gs_destroy.argtypes = [vp]
     lib.gs_destroy.restype = None
     lib.gs_get_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
@@ -231,7 +259,7 @@ class Plan:
             raise ValueError(f"x must be a contiguous {dt} tensor with {self.N ** self.dim} elements")
         if y is None:
             y = torch.empty(self.M, dtype=dt, device=x.device)
-        flags = (GS_WEIGHTED if weighted else 0) | (GS_SORTED if sorted_order else 0) | (GS_APPLY_F64 if f64 else 0)
+        flags = _wflags(weighted) | (GS_SORTED if sorted_order else 0) | (GS_APPLY_F64 if f64 else 0)
         rc = _lib.gs_apply_T(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), flags,
                              _stream(stream))
         if rc:
@@ -245,7 +273,7 @@ class Plan:
             raise ValueError(f"u must be a contiguous {dt} tensor with {self.M} elements")
         if x is None:
             x = torch.empty(self.coef_shape(), dtype=dt, device=u.device)
-        flags = (GS_WEIGHTED if weighted else 0) | (GS_SORTED if sorted_order else 0) | (GS_APPLY_F64 if f64 else 0)
+        flags = _wflags(weighted) | (GS_SORTED if sorted_order else 0) | (GS_APPLY_F64 if f64 else 0)
         rc = _lib.gs_apply_TH(self.handle, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(x.data_ptr()), flags,
                               _stream(stream))
         if rc:
@@ -262,7 +290,9 @@ class Plan:
                 raise ValueError("warm_start needs x")
             x = torch.zeros(self.coef_shape(), dtype=torch.complex128, device=y.device)
         hist = np.zeros(max_iter + 1) if history else None
-        o = SolveOpts(rel_tol, max_iter, int(warm_start), int(refine_fp64), max_restarts, check_every,
+        # warm_start: False (x0 = 0), True (x holds x0) or "guarded" (x0 kept only if it beats x0 = 0)
+        ws = 2 if warm_start == "guarded" else int(bool(warm_start))
+        o = SolveOpts(rel_tol, max_iter, ws, int(refine_fp64), max_restarts, check_every,
                       _dptr(hist) if hist is not None else None, hist.size if hist is not None else 0)
         info = SolveInfo()
         rc = _lib.gs_solve(self.handle, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(x.data_ptr()),
@@ -270,7 +300,8 @@ class Plan:
         if rc < 0:
             raise GSError(rc, "gs_solve")
         res = {"status": rc, "iterations": info.iterations, "restarts": info.restarts,
-               "rel_residual": info.rel_residual, "rel_residual_fp64": info.rel_residual_fp64}
+               "rel_residual": info.rel_residual, "rel_residual_fp64": info.rel_residual_fp64,
+               "warm_start_used": bool(info.warm_start_used)}
         if hist is not None:
             res["history"] = hist[: info.iterations + 1].copy()
         return x, res
@@ -324,8 +355,155 @@ def gs_solve_batch(plans, ys, xs=None, rel_tol=1e-6, max_iter=500, refine_fp64=T
     if rc < 0:
         raise GSError(rc, "gs_solve_batch")
     res = [{"status": i.status, "iterations": i.iterations, "restarts": i.restarts,
-            "rel_residual": i.rel_residual, "rel_residual_fp64": i.rel_residual_fp64} for i in infos]
+            "rel_residual": i.rel_residual, "rel_residual_fp64": i.rel_residual_fp64,
+            "warm_start_used": bool(i.warm_start_used)} for i in infos]
     return xs, res
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class Cnn:
+    """The learned warm start network (see include/gs.h): a handle for
+    images of height x width and batches up to max_batch."""
+
+    def __init__(self, height, width, max_batch=1):
+        h = ctypes.c_void_p()
+        rc = _lib.gs_cnn_create(ctypes.byref(h), int(height), int(width), int(max_batch))
+        if rc:
+            raise GSError(rc, "gs_cnn_create")
+        self._h = h.value
+        self.height, self.width, self.max_batch = int(height), int(width), int(max_batch)
+        self.n_params = _lib.gs_cnn_param_count()
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("network destroyed")
+        return self._h
+
+    def _check(self, rc, where):
+        if rc:
+            raise GSError(rc, where)
+
+    def set_weights(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        if a.size != self.n_params:
+            raise ValueError(f"need {self.n_params} parameters")
+        self._check(_lib.gs_cnn_set_weights(self.handle, _fptr(a)), "gs_cnn_set_weights")
+
+    def _get(self, fn, where):
+        a = np.empty(self.n_params, dtype=np.float32)
+        self._check(fn(self.handle, _fptr(a)), where)
+        return a
+
+    def get_weights(self):
+        return self._get(_lib.gs_cnn_get_weights, "gs_cnn_get_weights")
+
+    def get_grads(self):
+        return self._get(_lib.gs_cnn_get_grads, "gs_cnn_get_grads")
+
+    @property
+    def input_scale(self):
+        s = ctypes.c_float()
+        self._check(_lib.gs_cnn_get_input_scale(self.handle, ctypes.byref(s)), "gs_cnn_get_input_scale")
+        return s.value
+
+    @input_scale.setter
+    def input_scale(self, s):
+        self._check(_lib.gs_cnn_set_input_scale(self.handle, float(s)), "gs_cnn_set_input_scale")
+
+    def get_state(self):
+        m = np.empty(self.n_params, dtype=np.float32)
+        v = np.empty(self.n_params, dtype=np.float32)
+        st = ctypes.c_int()
+        self._check(_lib.gs_cnn_get_state(self.handle, _fptr(m), _fptr(v), ctypes.byref(st)), "gs_cnn_get_state")
+        return m, v, st.value
+
+    def set_state(self, m, v, step):
+        m = np.ascontiguousarray(m, dtype=np.float32)
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        self._check(_lib.gs_cnn_set_state(self.handle, _fptr(m), _fptr(v), int(step)), "gs_cnn_set_state")
+
+    def _images(self, x, name):
+        import torch
+        if x.dtype not in (torch.complex64, torch.complex128) or not x.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous complex64 or complex128 tensor")
+        if x.dim() == 2:
+            x = x.unsqueeze(0)
+        if x.dim() != 3 or tuple(x.shape[1:]) != (self.height, self.width):
+            raise ValueError(f"{name} must have shape (batch, {self.height}, {self.width})")
+        return x
+
+    def forward(self, x, out=None, train=False, out_dtype=None, stream=None):
+        import torch
+        squeeze = x.dim() == 2
+        x = self._images(x, "x")
+        if out is None and not (train and out_dtype is None):
+            out = torch.empty(x.shape, dtype=out_dtype or x.dtype, device=x.device)
+        if out is not None:
+            out = self._images(out, "out")
+        flags = (GS_CNN_IN_F64 if x.dtype == torch.complex128 else 0) | (GS_CNN_TRAIN if train else 0)
+        if out is not None and out.dtype == torch.complex128:
+            flags |= GS_CNN_OUT_F64
+        rc = _lib.gs_cnn_forward(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                 ctypes.c_void_p(out.data_ptr() if out is not None else 0), x.shape[0], flags,
+                                 _stream(stream))
+        self._check(rc, "gs_cnn_forward")
+        if out is None:
+            return None
+        return out[0] if squeeze else out
+
+    def backward(self, target, stream=None, want_loss=True):
+        import torch
+        t = self._images(target, "target")
+        flags = GS_CNN_TGT_F64 if t.dtype == torch.complex128 else 0
+        loss = ctypes.c_double(float("nan"))
+        rc = _lib.gs_cnn_backward(self.handle, ctypes.c_void_p(t.data_ptr()), t.shape[0], flags,
+                                  ctypes.byref(loss) if want_loss else None, _stream(stream))
+        self._check(rc, "gs_cnn_backward")
+        return loss.value
+
+    def step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        self._check(_lib.gs_cnn_step(self.handle, lr, beta1, beta2, eps, _stream(stream)), "gs_cnn_step")
+
+    def save(self, path):
+        m, v, step = self.get_state()
+        np.savez(path, weights=self.get_weights(), m=m, v=v, step=np.int64(step),
+                 input_scale=np.float32(self.input_scale),
+                 shape=np.array([self.height, self.width], dtype=np.int64))
+
+    def load(self, path):
+        with np.load(path, allow_pickle=False) as z:
+            self.set_weights(z["weights"])
+            if "input_scale" in z:
+                self.input_scale = float(z["input_scale"])
+            if "m" in z and "v" in z:
+                self.set_state(z["m"], z["v"], int(z["step"]))
+
+    def destroy(self):
+        if self._h:
+            _lib.gs_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def cnn_he_init(seed, last_scale=0.1):
+    """He-normal initial weights (std sqrt(2 / (9 ci))) for the six layers,
+    the last one scaled by last_scale, as the flat FP32 parameter array."""
+    rng = np.random.default_rng(seed)
+    ch = [2, 32, 32, 32, 32, 32, 2]
+    parts = []
+    for l in range(6):
+        std = np.sqrt(2.0 / (9 * ch[l])) * (last_scale if l == 5 else 1.0)
+        parts.append((rng.standard_normal((3, 3, ch[l], ch[l + 1])) * std).reshape(-1))
+    return np.concatenate(parts).astype(np.float32)
 
 
 def gs_destroy(plan: Plan):

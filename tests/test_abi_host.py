@@ -140,3 +140,18 @@ def test_eval_basis_rejects_bad_input():
         gs.gs_eval_basis_1d(1, 2, np.array([0.0]))
     with pytest.raises(gs.GSError):
         gs.gs_boundary_filters(1)
+
+
+def test_cnn_argument_checks_without_gpu():
+    lib = gs.library()
+    assert lib.gs_cnn_param_count() == 38016
+    h = ctypes.c_void_p()
+    assert lib.gs_cnn_create(None, 8, 8, 1) == gs.GS_ERR_INVALID_ARG
+    assert lib.gs_cnn_create(ctypes.byref(h), 0, 8, 1) == gs.GS_ERR_INVALID_ARG
+    assert lib.gs_cnn_create(ctypes.byref(h), 8, 8, 0) == gs.GS_ERR_INVALID_ARG
+    x = ctypes.c_void_p(16)
+    assert lib.gs_cnn_forward(None, x, x, 1, 0, None) == gs.GS_ERR_INVALID_ARG
+    assert lib.gs_cnn_backward(None, x, 1, 0, None, None) == gs.GS_ERR_INVALID_ARG
+    assert lib.gs_cnn_step(None, 1e-3, 0.9, 0.999, 1e-8, None) == gs.GS_ERR_INVALID_ARG
+    assert lib.gs_cnn_set_weights(None, None) == gs.GS_ERR_INVALID_ARG
+    lib.gs_cnn_destroy(None)

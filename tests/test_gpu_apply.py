@@ -185,3 +185,39 @@ def test_mixed_plan_has_both_paths(gs):
         plan32.apply_T(to_dev(X, torch.complex128), f64=True)
     plan.destroy()
     plan32.destroy()
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+@pytest.mark.parametrize("prec", [0, 2])
+def test_full_weight_adjoint(gs, dim, prec):
+    """GS_WEIGHT_FULL: T^H W u and W T x (the warm-start network's input
+    A^H b = T^H W y), against the oracle's dense T with diag(mu)."""
+    say(f"[full weight] dim={dim} prec={prec}")
+    rng = np.random.default_rng(31 + dim)
+    if dim == 1:
+        J, p = 6, 3
+        xi = rng.uniform(-40, 40, 300)
+        T = basis.dense_T_1d(xi, J, p)
+        shape = (1 << J,)
+    else:
+        J, p = 4, 2
+        xi = rng.uniform(-9, 9, (500, 2))
+        T = basis.dense_T_2d(xi, J, p)
+        shape = (1 << J, 1 << J)
+    mu = rng.uniform(0.2, 3.0, xi.shape[0])
+    plan = gs.gs_plan(dim, J, p, xi, mu, precision=prec)
+    f64 = prec == 2
+    u = crandn(rng, xi.shape[0])
+    x = crandn(rng, shape)
+    got_adj = to_host(plan.apply_TH(to_dev(u, torch.complex128), weighted="full", f64=f64))
+    got_fwd = to_host(plan.apply_T(to_dev(x, torch.complex128), weighted="full", f64=f64))
+    assert rel(got_adj.reshape(-1), T.conj().T @ (mu * u)) < 1e-12
+    assert rel(got_fwd, mu * (T @ x.reshape(-1))) < 1e-12
+    # the full-weight flag alone (without GS_WEIGHTED) is rejected
+    import ctypes
+    xin = to_dev(x, torch.complex128)
+    yout = torch.empty(xi.shape[0], dtype=torch.complex128, device="cuda")
+    rc = gs.library().gs_apply_T(plan.handle, ctypes.c_void_p(xin.data_ptr()), ctypes.c_void_p(yout.data_ptr()),
+                                 gs.GS_WEIGHT_FULL | (gs.GS_APPLY_F64 if f64 else 0), None)
+    assert rc == gs.GS_ERR_INVALID_ARG
+    plan.destroy()

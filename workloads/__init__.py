@@ -20,14 +20,14 @@ the same shapes and structure:
 """
 from .patterns import grid, jitter_1d, spiral_2d, jitter_2d
 from .weights import voronoi_weights_1d, voronoi_weights_2d
-from .phantom import ellipse_phantom_params, phantom_cell_averages
+from .phantom import ellipse_phantom_params, phantom_cell_averages, phantom_cell_averages_torch
 from .configs import (config_c1, config_c2, config_c3, config_c4_problem, config_c5_pattern,
                       complex_noise, relative_noise)
 
 __all__ = [
     "grid", "jitter_1d", "spiral_2d", "jitter_2d",
     "voronoi_weights_1d", "voronoi_weights_2d",
-    "ellipse_phantom_params", "phantom_cell_averages",
+    "ellipse_phantom_params", "phantom_cell_averages", "phantom_cell_averages_torch",
     "config_c1", "config_c2", "config_c3", "config_c4_problem", "config_c5_pattern",
     "complex_noise", "relative_noise",
 ]
