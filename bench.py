@@ -11,10 +11,12 @@ reported: FP64 apply pairs/s, per-kernel times (HIP events on the launch
 stream), the roofline of the dominant kernel, the plan ("init") time,
 wall time to relative normal residual 1e-6 for the plain FP64 and the
 FP32-mixed CGLS, the batched solve of 64 uneven 2D problems (against the
-same solves one after the other), and the FP64 CPU oracle timed on a
-bounded sample.
+same solves one after the other), the warm-start network (inference and
+training throughput, conv roofline, and zero- against warm-start CGLS when
+trained weights are present), and the FP64 CPU oracle timed on a bounded
+sample.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--no-cpu] [--no-batch]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--no-cpu] [--no-batch] [--no-cnn]
 """
 from __future__ import annotations
 
@@ -155,6 +157,91 @@ def batch_c4(gs, torch, dev, n_problems):
     return out
 
 
+CNN_WEIGHTS = os.path.join(ROOT, "paper_1607_04091_amd", "weights", "c5_cnn.npz")
+
+
+def cnn_bench(gs, torch, dev, batch, steps, n_eval):
+    """The learned warm start on its workload (db4, J = 8, 256 x 256, 64 x 4096
+    spiral points, radius 128, Voronoi weights): network throughput for
+    inference and training on batches of 256 x 256 images, per-kernel times,
+    the roofline of the hidden-layer convolution, and -- with trained weights
+    present -- zero-start against warm-start CGLS to 1e-6 on held-out
+    phantoms (seeds 70000...)."""
+    from paper_1607_04091_amd import warmstart as ws
+    H = W = 256
+    net = gs.Cnn(H, W, batch)
+    trained = os.path.exists(CNN_WEIGHTS)
+    if trained:
+        net.load(CNN_WEIGHTS)
+    else:
+        net.set_weights(gs.cnn_he_init(7, last_scale=0.1))
+    rng = np.random.default_rng(9)
+    x = torch.from_numpy((rng.standard_normal((batch, H, W)) + 1j * rng.standard_normal((batch, H, W)))
+                         .astype(np.complex64)).to(dev)
+    t = x * 0.5
+    out = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, n, warm=3):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    ms_inf = timed(lambda: net.forward(x, out, stream=stream), steps)
+
+    def train_step():
+        net.forward(x, train=True, stream=stream)
+        net.backward(t, stream=stream, want_loss=False)
+        net.step(1e-6, stream=stream)
+
+    ms_train = timed(train_step, max(3, steps // 2))
+    gs.gs_profile_enable(True)
+    nprof = 5
+    for _ in range(nprof):
+        train_step()
+    torch.cuda.synchronize()
+    prof = gs.gs_profile_read()
+    gs.gs_profile_enable(False)
+    if trained:
+        net.load(CNN_WEIGHTS)                   # undo the timing steps
+    kern = {k: {"launches": n, "avg_us": 1000.0 * tt / n} for k, (n, tt) in prof.items() if k.startswith("cnn_")}
+    flop_img = 2 * H * W * 9 * (2 * 32 + 4 * 32 * 32 + 32 * 2)
+    conv = kern.get("cnn_conv32")
+    roof = None
+    if conv:
+        byts = batch * H * W * 64 * 2           # read and write one bf16 activation tensor per launch
+        ach = byts / (conv["avg_us"] * 1e-6) / 1e9
+        fl = batch * 2 * H * W * 9 * 32 * 32 / (conv["avg_us"] * 1e-6) / 1e12
+        roof = {"kernel": "cnn_conv32", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "tflops_bf16": round(fl, 1),
+                "mfma_frac_bf16": round(fl / 2500.0, 4), "avg_launch_us": round(conv["avg_us"], 2),
+                "algorithmic_bytes_per_launch": int(byts)}
+    for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["avg_us"] * kv[1]["launches"]):
+        log(f"[bench]   {k:20s} {v['launches']:5d} launches  avg {v['avg_us']:9.2f} us")
+    res = {"batch": batch, "image": [H, W], "inference_ms": round(ms_inf, 3),
+           "inference_images_per_s": round(batch * 1000 / ms_inf, 1),
+           "inference_tflops": round(batch * flop_img / (ms_inf * 1e-3) / 1e12, 2),
+           "train_step_ms": round(ms_train, 3), "train_images_per_s": round(batch * 1000 / ms_train, 1),
+           "kernels_us": {k: round(v["avg_us"], 2) for k, v in kern.items()}, "conv_roofline": roof,
+           "trained_weights": trained}
+    log(f"[bench] cnn: inference {ms_inf:.3f} ms / {batch} images, training step {ms_train:.3f} ms")
+    if trained and n_eval > 0:
+        plans, c = ws.c5_plans(1)
+        rows = ws.evaluate(plans[0], net, np.arange(70000, 70000 + n_eval), c["J"])
+        res["warm_vs_zero"] = ws.summarize(rows)
+        log(f"[bench] warm start: {res['warm_vs_zero']}")
+        plans[0].destroy()
+    net.destroy()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +251,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-problems", type=int, default=64)
+    ap.add_argument("--no-cnn", action="store_true")
+    ap.add_argument("--warm-eval", type=int, default=10)
     ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--arms", type=int, default=64)
     ap.add_argument("--per-arm", type=int, default=16384)
@@ -292,6 +381,12 @@ def main():
         if not args.no_batch:
             solve["batched_c4"] = batch_c4(gs, torch, dev, args.batch_problems)
 
+    cnn = None
+    if not args.no_cnn:
+        cnn = cnn_bench(gs, torch, dev, 16, 20, 0 if args.no_solve else args.warm_eval)
+        if "warm_vs_zero" in cnn:
+            solve["warm_start"] = cnn["warm_vs_zero"]
+
     cpu = None
     if not args.no_cpu:
         cpu = oracle_baseline(pts, mu, J, p, min(args.cpu_sample, M), M)
@@ -319,6 +414,7 @@ def main():
         "roofline": roof,
         "pair_roofline": pair_roof,
         "solve": solve,
+        "cnn": cnn,
         "cpu_baseline": cpu,
     }
     plan.destroy()

@@ -178,7 +178,9 @@ std::vector<size_t> g_prof_open;
 const char* const kKernelNames[K_COUNT] = {
     "fft_rows_T", "fft_cols_T", "fft_sidecols_T", "interp2d", "interp1d", "fft1_T",
     "adj_prep", "boundary_partial", "boundary_final", "spread2d", "side_rows_partial", "side_cols_partial",
-    "reduce_strips", "fft_cols_TH", "fft_rows_TH", "fft_sidecols_TH", "spread1d", "fft1_TH", "merge_tiles", "boundary2d", "interp_bnd2d"};
+    "reduce_strips", "fft_cols_TH", "fft_rows_TH", "fft_sidecols_TH", "spread1d", "fft1_TH", "merge_tiles", "boundary2d", "interp_bnd2d",
+    "cnn_first", "cnn_conv32", "cnn_last", "cnn_loss", "cnn_last_bwd", "cnn_conv32_bwd", "cnn_dw32", "cnn_dw_thin",
+    "cnn_adam"};
 
 void prof_clear() {
     for (auto& r : g_prof_recs) {

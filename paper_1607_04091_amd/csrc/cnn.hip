@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "prof.hpp"
 
 namespace gs {
 namespace cnn {
@@ -679,16 +680,22 @@ extern "C" int gs_cnn_forward(gs_cnn_t* c, const void* in, void* out, int batch,
     const int64_t np = pix_count(n, batch);
     const int tx = (n.W + TS - 1) / TS, ty = (n.H + TS - 1) / TS;
     const int tiles = tx * ty * batch;
+    {
+    ProfScope _p(K_CNN_FIRST, st);
     if (flags & GS_CNN_IN_F64)
         hipLaunchKernelGGL((first_kernel<double>), dim3(nblk(np)), dim3(256), 0, st, (const double*)in, n.in_scale, n.x0,
                            n.act[0], n.wq1, batch, n.H, n.W);
     else
         hipLaunchKernelGGL((first_kernel<float>), dim3(nblk(np)), dim3(256), 0, st, (const float*)in, n.in_scale, n.x0,
                            n.act[0], n.wq1, batch, n.H, n.W);
-    for (int l = 0; l < 4; ++l)
+    }
+    for (int l = 0; l < 4; ++l) {
+        ProfScope _p(K_CNN_CONV, st);
         hipLaunchKernelGGL((conv32_kernel<0>), dim3(tiles), dim3(256), 0, st, n.act[l], n.fwd + l * PACK,
                            n.act[l + 1], (const uint16_t*)nullptr, batch, n.H, n.W, tx, ty);
+    }
     float* outf = (flags & GS_CNN_TRAIN) ? n.outf : nullptr;
+    ProfScope _p(K_CNN_LAST, st);
     if (flags & GS_CNN_OUT_F64)
         hipLaunchKernelGGL((last_kernel<double>), dim3(nblk(np)), dim3(256), 0, st, n.act[4], n.x0, n.wq6, outf,
                            (double*)out, batch, n.H, n.W);
@@ -713,6 +720,8 @@ extern "C" int gs_cnn_backward(gs_cnn_t* c, const void* target, int batch, int f
     const int segs_x = (n.W + THIN_SEG - 1) / THIN_SEG;
     const int thin_wg = (int)std::min<int64_t>(THIN_WG, (int64_t)batch * n.H * segs_x);
     // loss and d6
+    {
+    ProfScope _p(K_CNN_LOSS, st);
     if (flags & GS_CNN_TGT_F64) {
         hipLaunchKernelGGL((loss_partial_kernel<double>), dim3(LOSS_B), dim3(256), 0, st, n.outf,
                            (const double*)target, 2 * np, n.lpart);
@@ -726,27 +735,42 @@ extern "C" int gs_cnn_backward(gs_cnn_t* c, const void* target, int batch, int f
         hipLaunchKernelGGL((delta_out_kernel<float>), dim3(nblk(2 * np)), dim3(256), 0, st, n.outf,
                            (const float*)target, n.lscal, n.d6, 2 * np);
     }
+    }
     // layer 6: weight gradient, then data gradient into d5
-    hipLaunchKernelGGL((dw_thin_kernel<CH, 2, uint16_t, float>), dim3(thin_wg), dim3(576), 0, st, n.act[4], n.d6,
-                       n.part, batch, n.H, n.W, segs_x);
-    hipLaunchKernelGGL(dw_reduce_kernel, dim3(nblk(P6)), dim3(256), 0, st, n.part, thin_wg, P6, n.g + poff(5));
-    hipLaunchKernelGGL(last_bwd_kernel, dim3(nblk(np)), dim3(256), 0, st, n.d6, n.wq6, n.act[4], n.dl[0], batch,
-                       n.H, n.W);
+    {
+        ProfScope _p(K_CNN_DW_THIN, st);
+        hipLaunchKernelGGL((dw_thin_kernel<CH, 2, uint16_t, float>), dim3(thin_wg), dim3(576), 0, st, n.act[4],
+                           n.d6, n.part, batch, n.H, n.W, segs_x);
+        hipLaunchKernelGGL(dw_reduce_kernel, dim3(nblk(P6)), dim3(256), 0, st, n.part, thin_wg, P6, n.g + poff(5));
+    }
+    {
+        ProfScope _p(K_CNN_LAST_BWD, st);
+        hipLaunchKernelGGL(last_bwd_kernel, dim3(nblk(np)), dim3(256), 0, st, n.d6, n.wq6, n.act[4], n.dl[0], batch,
+                           n.H, n.W);
+    }
     // hidden layers 5..2 (1-based): weight gradient, then masked data gradient
     int cur = 0;
     for (int l = 5; l >= 2; --l) {
         const uint16_t* a_prev = n.act[l - 2];
-        hipLaunchKernelGGL(dw32_kernel, dim3(dw_wg), dim3(256), 0, st, a_prev, n.dl[cur], n.part, batch, n.H, n.W, tx,
-                           ty);
-        hipLaunchKernelGGL(dw_reduce_kernel, dim3(nblk(PH)), dim3(256), 0, st, n.part, dw_wg, PH, n.g + poff(l - 1));
+        {
+            ProfScope _p(K_CNN_DW, st);
+            hipLaunchKernelGGL(dw32_kernel, dim3(dw_wg), dim3(256), 0, st, a_prev, n.dl[cur], n.part, batch, n.H, n.W,
+                               tx, ty);
+            hipLaunchKernelGGL(dw_reduce_kernel, dim3(nblk(PH)), dim3(256), 0, st, n.part, dw_wg, PH,
+                               n.g + poff(l - 1));
+        }
+        ProfScope _p(K_CNN_CONV_BWD, st);
         hipLaunchKernelGGL((conv32_kernel<1>), dim3(tiles), dim3(256), 0, st, n.dl[cur], n.bwd + (l - 2) * PACK,
                            n.dl[cur ^ 1], a_prev, batch, n.H, n.W, tx, ty);
         cur ^= 1;
     }
     // layer 1: weight gradient from the FP32 input and d1
-    hipLaunchKernelGGL((dw_thin_kernel<2, CH, float, uint16_t>), dim3(thin_wg), dim3(576), 0, st, n.x0, n.dl[cur],
-                       n.part, batch, n.H, n.W, segs_x);
-    hipLaunchKernelGGL(dw_reduce_kernel, dim3(nblk(P1)), dim3(256), 0, st, n.part, thin_wg, P1, n.g + poff(0));
+    {
+        ProfScope _p(K_CNN_DW_THIN, st);
+        hipLaunchKernelGGL((dw_thin_kernel<2, CH, float, uint16_t>), dim3(thin_wg), dim3(576), 0, st, n.x0,
+                           n.dl[cur], n.part, batch, n.H, n.W, segs_x);
+        hipLaunchKernelGGL(dw_reduce_kernel, dim3(nblk(P1)), dim3(256), 0, st, n.part, thin_wg, P1, n.g + poff(0));
+    }
     if (hipGetLastError() != hipSuccess) return GS_ERR_HIP;
     if (loss) {
         if (hipMemcpyAsync(n.host, n.lscal, 4 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -765,6 +789,7 @@ extern "C" int gs_cnn_step(gs_cnn_t* c, float lr, float beta1, float beta2, floa
     n.step += 1;
     const float bc1 = (float)(1.0 - std::pow((double)beta1, n.step));
     const float bc2 = (float)(1.0 - std::pow((double)beta2, n.step));
+    ProfScope _p(K_CNN_STEP, st);
     hipLaunchKernelGGL(adam_kernel, dim3(nblk(NPARAM)), dim3(256), 0, st, n.w, n.m, n.v, n.g, NPARAM, lr, beta1,
                        beta2, eps, bc1, bc2);
     hipLaunchKernelGGL(pack_kernel, dim3(nblk(4 * PACK)), dim3(256), 0, st, n.w, n.fwd, n.bwd, n.wq1, n.wq6);

@@ -56,11 +56,12 @@ def _noisy_data(plan, x0, noise_rel, seed):
     return y
 
 
-def generate(plans, seeds, J, noise_rel=1e-4, tol=1e-6, max_iter=1000, log=None):
+def generate(plans, seeds, J, noise_rel=1e-4, tol=1e-6, max_iter=1000, log=None, seconds=None):
     """Training pairs for phantoms with the given seeds.  plans: several
     plans of one sampling pattern (FP32-mixed), solved together.  Returns
     (inputs, targets) as complex64 (n, N, N) device tensors and the CGLS
-    iteration counts."""
+    iteration counts.  With `seconds`, stops early (after a whole chunk) once
+    that much time has passed and returns the pairs made so far."""
     import torch
     from workloads import ellipse_phantom_params, phantom_cell_averages_torch
     dev = torch.device("cuda")
@@ -70,7 +71,10 @@ def generate(plans, seeds, J, noise_rel=1e-4, tol=1e-6, max_iter=1000, log=None)
     targets = torch.empty((n, N, N), dtype=torch.complex64, device=dev)
     iters = []
     t0 = time.time()
+    done = 0
     for start in range(0, n, K):
+        if seconds is not None and time.time() - t0 > seconds:
+            break
         chunk = seeds[start:start + K]
         x0s = phantom_cell_averages_torch([ellipse_phantom_params(int(s)) for s in chunk], J, dev)
         ys = []
@@ -83,9 +87,10 @@ def generate(plans, seeds, J, noise_rel=1e-4, tol=1e-6, max_iter=1000, log=None)
         for k in range(len(chunk)):
             targets[start + k] = xs[k].to(torch.complex64)
             iters.append(infos[k]["iterations"])
+        done = start + len(chunk)
         if log and (start // K) % max(1, (n // K) // 10) == 0:
             log(f"[warmstart] data {start + len(chunk)}/{n} ({time.time() - t0:.1f} s)")
-    return inputs, targets, iters
+    return inputs[:done], targets[:done], iters
 
 
 def fit_input_scale(inputs, targets, count=64):
@@ -214,6 +219,8 @@ def main(argv=None):
     t.add_argument("--batch", type=int, default=16)
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--plans", type=int, default=8)
+    t.add_argument("--data-seconds", type=float, default=None,
+                   help="stop making training pairs after this many seconds")
     args = ap.parse_args(argv)
     import torch
     if not torch.cuda.is_available():
@@ -225,9 +232,9 @@ def main(argv=None):
     N = 1 << J
     _log(f"[warmstart] {len(plans)} plans, M={plans[0].M}, J={J} ({time.time() - t0:.1f} s)")
     tr_seeds = np.arange(50000, 50000 + args.train)
-    inputs, targets, iters = generate(plans, tr_seeds, J, log=_log)
+    inputs, targets, iters = generate(plans, tr_seeds, J, log=_log, seconds=args.data_seconds)
     t_data = time.time() - t0
-    _log(f"[warmstart] training data: {args.train} pairs, mean CGLS iterations {np.mean(iters):.1f} "
+    _log(f"[warmstart] training data: {inputs.shape[0]} pairs, mean CGLS iterations {np.mean(iters):.1f} "
          f"({t_data:.1f} s)")
     net = gs.Cnn(N, N, args.batch)
     net.set_weights(gs.cnn_he_init(7, last_scale=0.1))
@@ -243,7 +250,7 @@ def main(argv=None):
         pl.destroy()
     rows = evaluate(plans[0], net, np.arange(70000, 70000 + args.test), J, log=_log)
     summ = summarize(rows)
-    meta = {"train_pairs": args.train, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+    meta = {"train_pairs": int(len(iters)), "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
             "data_s": round(t_data, 1), "train_s": round(t_train, 1), "input_scale": net.input_scale,
             "loss_history": hist, "target_iters_mean": float(np.mean(iters)), "eval": summ}
     with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
