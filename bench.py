@@ -158,6 +158,137 @@ def batch_c4(gs, torch, dev, n_problems):
 
 
 CNN_WEIGHTS = os.path.join(ROOT, "paper_1607_04091_amd", "weights", "c5_cnn.npz")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "c3_spiral1M_traffic.json")
+KERNEL_SOURCES = ["paper_1607_04091_amd/csrc/nfft2d.hip", "paper_1607_04091_amd/csrc/nfft.hip",
+                  "paper_1607_04091_amd/csrc/fft.hpp", "paper_1607_04091_amd/csrc/common.hpp",
+                  "paper_1607_04091_amd/csrc/cnn.hip"]
+# bench kernel name -> substrings of the device kernel names (FP32 instances)
+PMC_KERNELS = {
+    "spread2d": ["adj_interior_kernel<float"], "boundary2d": ["adj_boundary_kernel<float"],
+    "interp_bnd2d": ["interp_bnd_kernel<float"], "interp2d": ["interp_tile_kernel<float"],
+    "adj_prep": ["adj_gather_kernel<float"], "merge_tiles": ["merge_grid_kernel<float", "merge_sides_kernel<float"],
+    "cnn_conv32": ["conv32_kernel<0"],
+}
+COPY_MIB = 512
+
+
+def _sources_sha1():
+    import hashlib
+    out = {}
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            out[f] = hashlib.sha1(fh.read()).hexdigest()
+    return out
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when absent or when a kernel source changed since it was taken."""
+    if not os.path.exists(TRAFFIC_JSON):
+        return None
+    with open(TRAFFIC_JSON) as f:
+        t = json.load(f)
+    if t.get("sources") != _sources_sha1():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k["traffic_bytes"]
+
+
+def pmc_run():
+    """Workload for the counter passes: 3 FP32 apply pairs at the 1M-point
+    spiral shape, 3 network forwards (batch 16, 256 x 256) and 3 plain copies
+    of 512 MiB (an elementwise negation: reads and writes 512 MiB) that
+    calibrate FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    from paper_1607_04091_amd import gs
+    from workloads import spiral_2d, voronoi_weights_2d
+    dev = torch.device("cuda:0")
+    pts = spiral_2d(64, 16384, 256.0, 0.5)
+    mu = voronoi_weights_2d(pts, "disk", 256.25, 0.4)
+    plan = gs.gs_plan(2, 9, 4, pts, mu, precision=gs.GS_F32_MIXED)
+    rng = np.random.default_rng(5)
+    M, N = pts.shape[0], 512
+    x = torch.from_numpy((rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))).astype(np.complex64)).to(dev)
+    u = torch.from_numpy((rng.standard_normal(M) + 1j * rng.standard_normal(M)).astype(np.complex64)).to(dev)
+    for _ in range(3):
+        plan.apply_T(x, weighted=True)
+        plan.apply_TH(u, weighted=True)
+    net = gs.Cnn(256, 256, 16)
+    net.set_weights(gs.cnn_he_init(7, last_scale=0.1))
+    img = torch.zeros((16, 256, 256), dtype=torch.complex64, device=dev)
+    for _ in range(3):
+        net.forward(img)
+    n = COPY_MIB * 2 ** 20 // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    plan.destroy()
+    net.destroy()
+    print(json.dumps({"pmc_run": True}), flush=True)
+
+
+def traffic_from(fetch_dir, write_dir, command):
+    """Reads the counter CSVs of a FETCH_SIZE pass and a WRITE_SIZE pass,
+    scales each by the copy kernel's reading of its known 512 MiB, and writes
+    the per-launch HBM bytes of the kernels to profiles/ (JSON for bench.py,
+    and a short table)."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        vals = {}
+        for fn in files:
+            with open(fn) as f:
+                for row in csv.DictReader(f):
+                    if row.get("Counter_Name") != counter:
+                        continue
+                    vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+        return vals
+
+    fetch = per_kernel(fetch_dir, "FETCH_SIZE")
+    write = per_kernel(write_dir, "WRITE_SIZE")
+
+    def avg(vals, subs):
+        tot, ok = 0.0, False
+        for sub in subs:
+            hits = [v for k, v in vals.items() if sub in k]
+            if hits:
+                ok = True
+                tot += float(np.mean(hits[0]))
+        return tot if ok else None
+
+    copy_sub = ["neg_kernel", "neg"]
+    fc = next((avg(fetch, [c]) for c in copy_sub if avg(fetch, [c]) is not None), None)
+    wc = next((avg(write, [c]) for c in copy_sub if avg(write, [c]) is not None), None)
+    if not fc or not wc:
+        raise SystemExit("copy kernel not found in the counter output")
+    kib = COPY_MIB * 1024.0
+    cal = {"copy_mib": COPY_MIB, "fetch_kib": fc, "write_kib": wc, "fetch_scale": kib / fc, "write_scale": kib / wc}
+    out = {"command": command, "calibration": cal, "sources": _sources_sha1(), "kernels": {}}
+    for name, subs in PMC_KERNELS.items():
+        f, w = avg(fetch, subs), avg(write, subs)
+        if f is None or w is None:
+            continue
+        fb, wb = f * 1024 * cal["fetch_scale"], w * 1024 * cal["write_scale"]
+        out["kernels"][name] = {"fetch_kib": f, "write_kib": w, "fetch_bytes": fb, "write_bytes": wb,
+                                "traffic_bytes": fb + wb}
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(out, f, indent=1)
+    lines = ["# HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated)", "",
+             f"Command: `{command}`", "",
+             f"Calibration: a {COPY_MIB} MiB elementwise copy reads {fc:.0f} KiB and writes {wc:.0f} KiB per "
+             f"dispatch; scale factors {cal['fetch_scale']:.4f} (fetch), {cal['write_scale']:.4f} (write).", "",
+             "| kernel | FETCH KiB | WRITE KiB | traffic MB (scaled) |", "|---|---|---|---|"]
+    for name, k in out["kernels"].items():
+        lines.append(f"| {name} | {k['fetch_kib']:.0f} | {k['write_kib']:.0f} | {k['traffic_bytes'] / 1e6:.1f} |")
+    with open(TRAFFIC_JSON.replace(".json", ".md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(json.dumps(out["kernels"], indent=1))
 
 
 def cnn_bench(gs, torch, dev, batch, steps, n_eval):
@@ -220,7 +351,8 @@ def cnn_bench(gs, torch, dev, batch, steps, n_eval):
         ach = byts / (conv["avg_us"] * 1e-6) / 1e9
         fl = batch * 2 * H * W * 9 * 32 * 32 / (conv["avg_us"] * 1e-6) / 1e12
         roof = {"kernel": "cnn_conv32", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "tflops_bf16": round(fl, 1),
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic("cnn_conv32"),
+                "tflops_bf16": round(fl, 1),
                 "mfma_frac_bf16": round(fl / 2500.0, 4), "avg_launch_us": round(conv["avg_us"], 2),
                 "algorithmic_bytes_per_launch": int(byts)}
     for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["avg_us"] * kv[1]["launches"]):
@@ -256,7 +388,16 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--arms", type=int, default=64)
     ap.add_argument("--per-arm", type=int, default=16384)
+    ap.add_argument("--pmc-run", action="store_true", help="only the short workload for counter passes")
+    ap.add_argument("--traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COMMAND"),
+                    help="turn two counter passes into profiles/c3_spiral1M_traffic.{json,md} (no GPU)")
     args = ap.parse_args()
+    if args.traffic:
+        traffic_from(*args.traffic)
+        return
+    if args.pmc_run:
+        pmc_run()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the point-sharded design "
               "is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
@@ -342,7 +483,7 @@ def main():
     if ab is not None:
         ach = ab / (kernels[dom]["avg_us"] * 1e-6) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
                 "algorithmic_bytes_per_launch": int(ab), "avg_launch_us": round(kernels[dom]["avg_us"], 2)}
     for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["avg_us"] * kv[1]["launches"]):
         log(f"[bench]   {k:20s} {v['launches']:5d} launches  avg {v['avg_us']:9.2f} us"

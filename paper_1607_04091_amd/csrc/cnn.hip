@@ -50,7 +50,7 @@ constexpr int TS = 16;                        // output tile side of the MFMA ke
 constexpr int HALO = TS + 2;
 constexpr int PSTR = 36;                      // LDS pixel stride, halfwords (72 B: conflict-free 8 B reads)
 constexpr int DW_WG = 512;                    // weight-gradient workgroups (partials)
-constexpr int THIN_WG = 512;
+constexpr int THIN_WG = 1024;                 // thin-gradient workgroups (one partial each)
 constexpr int THIN_SEG = 64;                  // pixels per row segment in the thin gradient kernel
 constexpr int LOSS_B = 256;
 constexpr int DSTR = 260;                     // transposed delta tile: channel stride, halfwords
@@ -441,48 +441,91 @@ __global__ void __launch_bounds__(256) dw32_kernel(const uint16_t* __restrict__ 
 }
 
 // ------------------------------------------------------------------ thin-layer weight gradients, ALU
-// dW[t][ci][co] = sum_p U[p + t][ci] V[p][co] with 9 * CU * CV = 576 outputs, one
-// per thread; row segments of 64 pixels staged in LDS; one partial per workgroup
+// dW[t][cu][cv] = sum_p U[p + t][cu] V[p][cv] with CU * CV = 64: lane (cu, cv)
+// of a wave owns the 9 taps of one (cu, cv) pair.  A wave walks row segments in
+// chunks of THIN_CH pixels: it loads the chunk's 3 x (THIN_CH + 2) values of U
+// and THIN_CH values of V into registers at once (lanes sharing cu or cv read
+// the same addresses), then does the 9 THIN_CH FMAs.  The four waves of a
+// workgroup add their sums in LDS in a fixed order; one partial per workgroup.
+constexpr int THIN_CH = 16;
 template <int CU, int CV, class UT, class VT>
-__global__ void __launch_bounds__(576) dw_thin_kernel(const UT* __restrict__ U, const VT* __restrict__ V,
+__global__ void __launch_bounds__(256) dw_thin_kernel(const UT* __restrict__ U, const VT* __restrict__ V,
                                                       float* __restrict__ part, int B, int H, int W, int segs_x) {
-    static_assert(TAPS * CU * CV == 576, "one output per thread");
-    __shared__ float su[3][THIN_SEG + 2][CU];
-    __shared__ float sv[THIN_SEG][CV];
-    const int o = threadIdx.x;
-    const int co = o % CV, ci = (o / CV) % CU, tap = o / (CV * CU);
-    const int ky = tap / 3, kx = tap % 3;
-    float acc = 0.f;
+    static_assert(CU * CV == 64, "one (cu, cv) pair per lane");
+    __shared__ float red[4][TAPS * 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cu = lane / CV, cv = lane % CV;
     const int64_t nseg = (int64_t)B * H * segs_x;
-    for (int64_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+    float acc[TAPS];
+#pragma unroll
+    for (int t = 0; t < TAPS; ++t) acc[t] = 0.f;
+    for (int64_t sg = (int64_t)blockIdx.x * 4 + wave; sg < nseg; sg += (int64_t)gridDim.x * 4) {
         const int sx = (int)(sg % segs_x);
         const int y = (int)((sg / segs_x) % H);
         const int64_t b = sg / ((int64_t)segs_x * H);
         const int x0 = sx * THIN_SEG;
-        __syncthreads();
-        for (int i = threadIdx.x; i < 3 * (THIN_SEG + 2) * CU; i += 576) {
-            const int c = i % CU, px = (i / CU) % (THIN_SEG + 2), ry = i / (CU * (THIN_SEG + 2));
-            const int gy = y + ry - 1, gx = x0 + px - 1;
-            su[ry][px][c] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? ldv(U, ((b * H + gy) * W + gx) * CU + c) : 0.f;
+        const int x1 = min(W, x0 + THIN_SEG);
+        bool rowok[3];
+        int64_t rowbase[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const int yy = y + r - 1;
+            rowok[r] = yy >= 0 && yy < H;
+            rowbase[r] = (b * H + (rowok[r] ? yy : 0)) * (int64_t)W;
         }
-        for (int i = threadIdx.x; i < THIN_SEG * CV; i += 576) {
-            const int c = i % CV, px = i / CV;
-            const int gx = x0 + px;
-            sv[px][c] = gx < W ? ldv(V, ((b * H + y) * W + gx) * CV + c) : 0.f;
+        const int64_t vbase = (b * H + y) * (int64_t)W;
+        for (int xc = x0; xc < x1; xc += THIN_CH) {
+            float u[3][THIN_CH + 2], v[THIN_CH];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int k = 0; k < THIN_CH + 2; ++k) {
+                    const int x = xc - 1 + k;
+                    u[r][k] = (rowok[r] && x >= 0 && x < W) ? ldv(U, (rowbase[r] + x) * CU + cu) : 0.f;
+                }
+#pragma unroll
+            for (int k = 0; k < THIN_CH; ++k) v[k] = (xc + k < W) ? ldv(V, (vbase + xc + k) * CV + cv) : 0.f;
+#pragma unroll
+            for (int k = 0; k < THIN_CH; ++k)
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+#pragma unroll
+                    for (int kx = 0; kx < 3; ++kx) acc[r * 3 + kx] = fmaf(u[r][k + kx], v[k], acc[r * 3 + kx]);
         }
-        __syncthreads();
-#pragma unroll 8
-        for (int px = 0; px < THIN_SEG; ++px) acc = fmaf(su[ky][px + kx][ci], sv[px][co], acc);
     }
-    part[(int64_t)blockIdx.x * 576 + o] = acc;
+#pragma unroll
+    for (int t = 0; t < TAPS; ++t) red[wave][t * 64 + lane] = acc[t];
+    __syncthreads();
+    for (int i = threadIdx.x; i < TAPS * 64; i += 256) {
+        const int t = i >> 6, l = i & 63;
+        const float sum = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
+        part[(int64_t)blockIdx.x * (TAPS * 64) + (t * CU + l / CV) * CV + l % CV] = sum;
+    }
 }
 
-__global__ void __launch_bounds__(256) dw_reduce_kernel(const float* __restrict__ part, int nparts, int count,
-                                                        float* __restrict__ grad) {
+// Sum of nparts partials of `count` values in a fixed order, in two stages:
+// stage 1 sums the partials of each of RED_G groups (block (x, g) covers 256
+// consecutive values of group g), stage 2 sums the RED_G group sums.
+constexpr int RED_G = 32;
+__global__ void __launch_bounds__(256) dw_reduce1_kernel(const float* __restrict__ part, int nparts, int count,
+                                                         float* __restrict__ tmp) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int g = blockIdx.y;
+    if (i >= count) return;
+    const int per = (nparts + RED_G - 1) / RED_G;
+    const int p0 = g * per, p1 = min(nparts, p0 + per);
+    float s = 0.f;
+    for (int p = p0; p < p1; ++p) s += part[(int64_t)p * count + i];
+    tmp[(int64_t)g * count + i] = s;
+}
+
+__global__ void __launch_bounds__(256) dw_reduce2_kernel(const float* __restrict__ tmp, int count,
+                                                         float* __restrict__ grad) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= count) return;
     float s = 0.f;
-    for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * count + i];
+#pragma unroll 8
+    for (int g = 0; g < RED_G; ++g) s += tmp[(int64_t)g * count + i];
     grad[i] = s;
 }
 
@@ -533,7 +576,7 @@ struct Net {
     float *wq1 = nullptr, *wq6 = nullptr;
     uint16_t* act[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     uint16_t* dl[2] = {nullptr, nullptr};
-    float *x0 = nullptr, *outf = nullptr, *d6 = nullptr, *part = nullptr;
+    float *x0 = nullptr, *outf = nullptr, *d6 = nullptr, *part = nullptr, *red = nullptr;
     double *lpart = nullptr, *lscal = nullptr, *host = nullptr;
     int step = 0;
     float in_scale = 1.f;      // fixed input scale (not trained)
@@ -599,6 +642,7 @@ extern "C" int gs_cnn_create(gs_cnn_t** out, int height, int width, int max_batc
     alloc(n.outf, np * 2);
     alloc(n.d6, np * 2);
     alloc(n.part, (int64_t)std::max(DW_WG * PH, THIN_WG * 576));
+    alloc(n.red, (int64_t)RED_G * PH);
     alloc(n.lpart, 2 * LOSS_B);
     alloc(n.lscal, 4);
     if (ok && hipHostMalloc((void**)&n.host, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) ok = false;
@@ -718,7 +762,12 @@ extern "C" int gs_cnn_backward(gs_cnn_t* c, const void* target, int batch, int f
     const int tiles = tx * ty * batch;
     const int dw_wg = std::min(DW_WG, tiles);
     const int segs_x = (n.W + THIN_SEG - 1) / THIN_SEG;
-    const int thin_wg = (int)std::min<int64_t>(THIN_WG, (int64_t)batch * n.H * segs_x);
+    const int thin_wg = (int)std::min<int64_t>(THIN_WG, ((int64_t)batch * n.H * segs_x + 3) / 4);
+    auto reduce = [&](int nparts, int count, float* out) {
+        hipLaunchKernelGGL(dw_reduce1_kernel, dim3(nblk(count), RED_G), dim3(256), 0, st, n.part, nparts, count,
+                           n.red);
+        hipLaunchKernelGGL(dw_reduce2_kernel, dim3(nblk(count)), dim3(256), 0, st, n.red, count, out);
+    };
     // loss and d6
     {
     ProfScope _p(K_CNN_LOSS, st);
@@ -739,9 +788,9 @@ extern "C" int gs_cnn_backward(gs_cnn_t* c, const void* target, int batch, int f
     // layer 6: weight gradient, then data gradient into d5
     {
         ProfScope _p(K_CNN_DW_THIN, st);
-        hipLaunchKernelGGL((dw_thin_kernel<CH, 2, uint16_t, float>), dim3(thin_wg), dim3(576), 0, st, n.act[4],
+        hipLaunchKernelGGL((dw_thin_kernel<CH, 2, uint16_t, float>), dim3(thin_wg), dim3(256), 0, st, n.act[4],
                            n.d6, n.part, batch, n.H, n.W, segs_x);
-        hipLaunchKernelGGL(dw_reduce_kernel, dim3(nblk(P6)), dim3(256), 0, st, n.part, thin_wg, P6, n.g + poff(5));
+        reduce(thin_wg, P6, n.g + poff(5));
     }
     {
         ProfScope _p(K_CNN_LAST_BWD, st);
@@ -756,8 +805,7 @@ extern "C" int gs_cnn_backward(gs_cnn_t* c, const void* target, int batch, int f
             ProfScope _p(K_CNN_DW, st);
             hipLaunchKernelGGL(dw32_kernel, dim3(dw_wg), dim3(256), 0, st, a_prev, n.dl[cur], n.part, batch, n.H, n.W,
                                tx, ty);
-            hipLaunchKernelGGL(dw_reduce_kernel, dim3(nblk(PH)), dim3(256), 0, st, n.part, dw_wg, PH,
-                               n.g + poff(l - 1));
+            reduce(dw_wg, PH, n.g + poff(l - 1));
         }
         ProfScope _p(K_CNN_CONV_BWD, st);
         hipLaunchKernelGGL((conv32_kernel<1>), dim3(tiles), dim3(256), 0, st, n.dl[cur], n.bwd + (l - 2) * PACK,
@@ -767,9 +815,9 @@ extern "C" int gs_cnn_backward(gs_cnn_t* c, const void* target, int batch, int f
     // layer 1: weight gradient from the FP32 input and d1
     {
         ProfScope _p(K_CNN_DW_THIN, st);
-        hipLaunchKernelGGL((dw_thin_kernel<2, CH, float, uint16_t>), dim3(thin_wg), dim3(576), 0, st, n.x0,
+        hipLaunchKernelGGL((dw_thin_kernel<2, CH, float, uint16_t>), dim3(thin_wg), dim3(256), 0, st, n.x0,
                            n.dl[cur], n.part, batch, n.H, n.W, segs_x);
-        hipLaunchKernelGGL(dw_reduce_kernel, dim3(nblk(P1)), dim3(256), 0, st, n.part, thin_wg, P1, n.g + poff(0));
+        reduce(thin_wg, P1, n.g + poff(0));
     }
     if (hipGetLastError() != hipSuccess) return GS_ERR_HIP;
     if (loss) {
