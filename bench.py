@@ -159,9 +159,9 @@ def batch_c4(gs, torch, dev, n_problems):
 
 CNN_WEIGHTS = os.path.join(ROOT, "paper_1607_04091_amd", "weights", "c5_cnn.npz")
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "c3_spiral1M_traffic.json")
-KERNEL_SOURCES = ["paper_1607_04091_amd/csrc/nfft2d.hip", "paper_1607_04091_amd/csrc/nfft.hip",
-                  "paper_1607_04091_amd/csrc/fft.hpp", "paper_1607_04091_amd/csrc/common.hpp",
-                  "paper_1607_04091_amd/csrc/cnn.hip"]
+PAIR_SOURCES = ["paper_1607_04091_amd/csrc/nfft2d.hip", "paper_1607_04091_amd/csrc/nfft.hip",
+                "paper_1607_04091_amd/csrc/fft.hpp", "paper_1607_04091_amd/csrc/common.hpp"]
+CNN_SOURCES = ["paper_1607_04091_amd/csrc/cnn.hip"]
 # bench kernel name -> substrings of the device kernel names (FP32 instances)
 PMC_KERNELS = {
     "spread2d": ["adj_interior_kernel<float"], "boundary2d": ["adj_boundary_kernel<float"],
@@ -172,10 +172,10 @@ PMC_KERNELS = {
 COPY_MIB = 512
 
 
-def _sources_sha1():
+def _sources_sha1(files):
     import hashlib
     out = {}
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             out[f] = hashlib.sha1(fh.read()).hexdigest()
     return out
@@ -188,10 +188,10 @@ def measured_traffic(kernel):
         return None
     with open(TRAFFIC_JSON) as f:
         t = json.load(f)
-    if t.get("sources") != _sources_sha1():
-        return None
     k = t.get("kernels", {}).get(kernel)
-    return None if k is None else k["traffic_bytes"]
+    if k is None or k.get("sources") != _sources_sha1(list(k.get("sources", {}))):
+        return None
+    return k["traffic_bytes"]
 
 
 def pmc_run():
@@ -269,14 +269,15 @@ def traffic_from(fetch_dir, write_dir, command):
         raise SystemExit("copy kernel not found in the counter output")
     kib = COPY_MIB * 1024.0
     cal = {"copy_mib": COPY_MIB, "fetch_kib": fc, "write_kib": wc, "fetch_scale": kib / fc, "write_scale": kib / wc}
-    out = {"command": command, "calibration": cal, "sources": _sources_sha1(), "kernels": {}}
+    out = {"command": command, "calibration": cal, "kernels": {}}
     for name, subs in PMC_KERNELS.items():
         f, w = avg(fetch, subs), avg(write, subs)
         if f is None or w is None:
             continue
         fb, wb = f * 1024 * cal["fetch_scale"], w * 1024 * cal["write_scale"]
+        src = CNN_SOURCES if name.startswith("cnn_") else PAIR_SOURCES
         out["kernels"][name] = {"fetch_kib": f, "write_kib": w, "fetch_bytes": fb, "write_bytes": wb,
-                                "traffic_bytes": fb + wb}
+                                "traffic_bytes": fb + wb, "sources": _sources_sha1(src)}
     with open(TRAFFIC_JSON, "w") as f:
         json.dump(out, f, indent=1)
     lines = ["# HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated)", "",
