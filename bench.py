@@ -292,6 +292,35 @@ def traffic_from(fetch_dir, write_dir, command):
     print(json.dumps(out["kernels"], indent=1))
 
 
+def c2_solves(gs, torch, dev):
+    """The 1D nonuniform workload (db4, J = 14, 65,536 jittered points,
+    Voronoi lengths): wall time to relative normal residual 1e-8 for the FP64
+    and the FP32-mixed solve, and the distance of the result from x0 (the data
+    y = T x0 are consistent and T has full column rank, so the LS solution is
+    x0).  y comes from the library's FP64 apply."""
+    from workloads import config_c2
+    c = config_c2()
+    out = {}
+    for name, prec in (("fp64", gs.GS_F64), ("fp32_mixed", gs.GS_F32_MIXED)):
+        pl = gs.gs_plan(1, c["J"], c["p"], c["xi"], c["mu"], precision=prec)
+        x0 = torch.from_numpy(c["x0"]).to(dev)
+        y = pl.apply_T(x0, f64=prec == gs.GS_F32_MIXED)
+        pl.solve(y, rel_tol=1e-8, max_iter=2)                      # warm-up of the code path
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = pl.solve(y, rel_tol=1e-8, max_iter=1000, refine_fp64=True, max_restarts=3, check_every=10)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        err = float(torch.linalg.vector_norm(x - x0).item() / torch.linalg.vector_norm(x0).item())
+        out[name] = {"wall_s": round(dt, 4), "iterations": info["iterations"], "status": info["status"],
+                     "rel_residual": info["rel_residual"], "rel_residual_fp64": info["rel_residual_fp64"],
+                     "rel_error_vs_x0": err}
+        log(f"[bench] C2 solve {name}: {dt * 1e3:.1f} ms, {info['iterations']} iterations, status {info['status']}, "
+            f"|x - x0|/|x0| {err:.2e}")
+        pl.destroy()
+    return out
+
+
 def cnn_bench(gs, torch, dev, batch, steps, n_eval):
     """The learned warm start on its workload (db4, J = 8, 256 x 256, 64 x 4096
     spiral points, radius 128, Voronoi weights): network throughput for
@@ -385,7 +414,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-problems", type=int, default=64)
     ap.add_argument("--no-cnn", action="store_true")
-    ap.add_argument("--warm-eval", type=int, default=10)
+    ap.add_argument("--warm-eval", type=int, default=100)
     ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--arms", type=int, default=64)
     ap.add_argument("--per-arm", type=int, default=16384)
@@ -502,6 +531,7 @@ def main():
         torch.cuda.synchronize()
         ynp = yclean.cpu().numpy()
         y = torch.from_numpy(ynp + relative_noise(ynp, 1e-4, 302)).to(dev)
+        sols = {}
         for name, prec in (("fp32_mixed", gs.GS_F32_MIXED), ("plain_fp64", gs.GS_F64)):
             pl = plan if prec == gs.GS_F32_MIXED else gs.gs_plan(2, J, p, pts, mu, precision=prec)
             xsol = torch.zeros((N, N), dtype=torch.complex128, device=dev)
@@ -517,9 +547,15 @@ def main():
                            "rel_residual": info["rel_residual"], "rel_residual_fp64": info["rel_residual_fp64"]}
             log(f"[bench] solve {name}: {dt:.3f} s, {info['iterations']} iterations, status {info['status']}, "
                 f"rr {info['rel_residual']:.2e}, rr64 {info['rel_residual_fp64']:.2e}")
+            sols[name] = xsol
             if pl is not plan:
                 pl.destroy()
+        # the mixed-form result against the plain FP64 solve of the same problem
+        d = torch.linalg.vector_norm(sols["fp32_mixed"] - sols["plain_fp64"]).item()
+        solve["fp32_mixed"]["rel_diff_vs_plain_fp64"] = d / torch.linalg.vector_norm(sols["plain_fp64"]).item()
+        log(f"[bench] mixed vs plain FP64 solution: {solve['fp32_mixed']['rel_diff_vs_plain_fp64']:.2e}")
         solve["warm_start"] = None
+        solve["c2_1d"] = c2_solves(gs, torch, dev)
         if not args.no_batch:
             solve["batched_c4"] = batch_c4(gs, torch, dev, args.batch_problems)
 

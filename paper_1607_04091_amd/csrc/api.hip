@@ -63,6 +63,11 @@ void free_plan(gs::Plan& P) {
     dfree(P.red); dfree(P.scal); dfree(P.hist);
     if (P.host_scal) (void)hipHostFree(P.host_scal);
     P.host_scal = nullptr;
+    if (P.ev_fork) (void)hipEventDestroy(P.ev_fork);
+    if (P.ev_join) (void)hipEventDestroy(P.ev_join);
+    if (P.side) (void)hipStreamDestroy(P.side);
+    P.ev_fork = P.ev_join = nullptr;
+    P.side = nullptr;
 }
 
 struct HostPoints {
@@ -348,6 +353,11 @@ int gs_plan(gs_plan_t** out, int dim, int J, int p, int64_t M, const double* xi,
             if ((e = upload_prec<float>(P, H, smu, gs::W32, gs::DEG32, 2.35 * gs::W32, s)) != hipSuccess) break;
         if ((e = gs::solver_alloc(P)) != hipSuccess) break;
         if ((e = hipMemcpy(P.smu64, smu.data(), M * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) break;
+        if (dim == 2 && P.nb > 0) {
+            if ((e = hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking)) != hipSuccess) break;
+            if ((e = hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming)) != hipSuccess) break;
+            if ((e = hipEventCreateWithFlags(&P.ev_join, hipEventDisableTiming)) != hipSuccess) break;
+        }
     } while (0);
     if (e != hipSuccess) {
         free_plan(P);

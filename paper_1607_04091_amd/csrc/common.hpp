@@ -105,6 +105,10 @@ struct Plan {
     int64_t bytes = 0;
     std::string last_error;
     hipStream_t upload_stream = nullptr;
+    // 2D adjoint: the column-side/corner kernel runs on `side` beside the
+    // interior kernel (fork/join by events; serial while a graph is captured)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 template <class T> PrecData<T>& prec(Plan& p);

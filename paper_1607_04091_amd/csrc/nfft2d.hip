@@ -855,17 +855,32 @@ hipError_t adjoint2d_tile_nb(const Plan& P, const cx<T>* u, cx<T>* x, int flags,
         hipLaunchKernelGGL((adj_gather_kernel<T>), dim3((P.M + 255) / 256), dim3(256), 0, s, g, u, flags, d.vbuf);
         GS_HIP_TRY(hipGetLastError());
     }
+    // The interior and the column-side/corner kernels read the same staged
+    // input and write disjoint partials: the second runs on the plan's side
+    // stream, joined before the merges.  Under graph capture both stay on s.
+    hipStream_t s2 = s;
+    if constexpr (NB > 0) {
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        GS_HIP_TRY(hipStreamIsCapturing(s, &cap));
+        if (P.side && cap == hipStreamCaptureStatusNone) {
+            GS_HIP_TRY(hipEventRecord(P.ev_fork, s));
+            GS_HIP_TRY(hipStreamWaitEvent(P.side, P.ev_fork, 0));
+            s2 = P.side;
+        }
+        ProfScope _p(K_BND2D, s2);
+        hipLaunchKernelGGL((adj_boundary_kernel<T, W, DEG, NB>), dim3(nt), dim3(BND_THREADS), 0, s2, g,
+                           (const cx<T>*)d.vbuf, partC, partX);
+        GS_HIP_TRY(hipGetLastError());
+    }
     {
         ProfScope _p(K_SPREAD2D, s);
         hipLaunchKernelGGL((adj_interior_kernel<T, W, DEG, NB>), dim3(nt), dim3(IntShape<W>::THREADS), 0, s, g,
                            (const cx<T>*)d.vbuf, partI, partR);
         GS_HIP_TRY(hipGetLastError());
     }
-    if constexpr (NB > 0) {
-        ProfScope _p(K_BND2D, s);
-        hipLaunchKernelGGL((adj_boundary_kernel<T, W, DEG, NB>), dim3(nt), dim3(BND_THREADS), 0, s, g,
-                           (const cx<T>*)d.vbuf, partC, partX);
-        GS_HIP_TRY(hipGetLastError());
+    if (s2 != s) {
+        GS_HIP_TRY(hipEventRecord(P.ev_join, s2));
+        GS_HIP_TRY(hipStreamWaitEvent(s, P.ev_join, 0));
     }
     {
         ProfScope _p(K_MERGE, s);
