@@ -487,9 +487,10 @@ int solve_impl(const Plan& P, const cx<double>* y, cx<double>* x, const gs_solve
 // ------------------------------------------------------------------ batched solve
 //
 // Many independent problems (each with its own plan) advance together.  The
-// CGLS iteration of every problem is captured once as a HIP graph; each round
-// launches the graphs of the problems still running, spread over several
-// streams, and every `check_every` rounds the host reads all stop flags
+// CGLS iteration of every problem is captured as HIP graphs (one iteration,
+// and min(check_every, 16) iterations back to back); each round launches the
+// graphs of the problems still running, spread over several streams, and
+// every `check_every` iterations the host reads all stop flags
 // (one synchronization for the whole batch) and drops the problems that are
 // done.  The update kernels also test the device flag, so a round that runs
 // past convergence changes nothing.  Problems go to streams heaviest first
@@ -501,14 +502,16 @@ struct BatchItem {
     const Plan* P;
     cx<double>* x;
     bool fp32;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // exec[0]: one CGLS iteration; exec[1]: `ipg` iterations back to back
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
     int stream = 0;
     bool active = true, done = false, broke = false;
     int warm_used = 0;
 };
 
-static hipError_t capture_iteration(BatchItem& it, const gs_solve_opts& opt, hipStream_t cs) {
+static hipError_t capture_iterations(BatchItem& it, int which, int iters, const gs_solve_opts& opt,
+                                     hipStream_t cs) {
     const Plan& P = *it.P;
     double* hist = opt.history ? P.hist : nullptr;
     const int hist_len = std::min(P.hist_len, opt.history_len);
@@ -520,15 +523,16 @@ static hipError_t capture_iteration(BatchItem& it, const gs_solve_opts& opt, hip
         g_prof_enabled = prof;
         return e;
     }
-    e = it.fp32 ? cgls_iteration<float>(P, it.x, cs, hist, hist_len)
-                : cgls_iteration<double>(P, it.x, cs, hist, hist_len);
+    for (int k = 0; k < iters && e == hipSuccess; ++k)
+        e = it.fp32 ? cgls_iteration<float>(P, it.x, cs, hist, hist_len)
+                    : cgls_iteration<double>(P, it.x, cs, hist, hist_len);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &g);
     g_prof_enabled = prof;
     if (e != hipSuccess) return e;
     if (e2 != hipSuccess) return e2;
-    it.graph = g;
-    return hipGraphInstantiate(&it.exec, g, nullptr, nullptr, 0);
+    it.graph[which] = g;
+    return hipGraphInstantiate(&it.exec[which], g, nullptr, nullptr, 0);
 }
 
 static void assign_streams(std::vector<BatchItem>& items, int ns) {
@@ -566,10 +570,11 @@ extern "C" int gs_solve_batch(const gs_plan_t* const* plans, int count, const vo
     std::vector<hipEvent_t> evs;
     int rc = GS_OK;
     auto cleanup = [&]() {
-        for (auto& it : items) {
-            if (it.exec) (void)hipGraphExecDestroy(it.exec);
-            if (it.graph) (void)hipGraphDestroy(it.graph);
-        }
+        for (auto& it : items)
+            for (int w = 0; w < 2; ++w) {
+                if (it.exec[w]) (void)hipGraphExecDestroy(it.exec[w]);
+                if (it.graph[w]) (void)hipGraphDestroy(it.graph[w]);
+            }
         for (auto e : evs) (void)hipEventDestroy(e);
         for (auto s : streams) (void)hipStreamDestroy(s);
     };
@@ -614,18 +619,26 @@ extern "C" int gs_solve_batch(const gs_plan_t* const* plans, int count, const vo
             return rc;
         }
     }
+    const int check_every = std::max(1, opts->check_every);
+    // iterations per graph launch: up to 16 captured back to back, the rest of
+    // a check interval from the one-iteration graph
+    const int ipg = std::min(check_every, 16);
     for (auto& it : items) {
-        hipError_t e = capture_iteration(it, *opts, streams[it.stream]);
+        hipError_t e = capture_iterations(it, 0, 1, *opts, streams[it.stream]);
+        if (e == hipSuccess && ipg > 1) e = capture_iterations(it, 1, ipg, *opts, streams[it.stream]);
         if (e != hipSuccess) return fail(e);
     }
-    const int check_every = std::max(1, opts->check_every);
     int ns = ns_max;
     int rounds = 0;
-    // one round: every active problem advances by one iteration
+    // n rounds: every active problem advances by n iterations
     auto run_rounds = [&](int n) -> hipError_t {
-        for (int r = 0; r < n; ++r)
+        const int full = ipg > 1 ? n / ipg : 0, rest = n - full * ipg;
+        for (int r = 0; r < full; ++r)
             for (auto& it : items)
-                if (it.active) GS_HIP_TRY(hipGraphLaunch(it.exec, streams[it.stream]));
+                if (it.active) GS_HIP_TRY(hipGraphLaunch(it.exec[1], streams[it.stream]));
+        for (int r = 0; r < rest; ++r)
+            for (auto& it : items)
+                if (it.active) GS_HIP_TRY(hipGraphLaunch(it.exec[0], streams[it.stream]));
         return hipSuccess;
     };
     auto check = [&]() -> hipError_t {
@@ -656,7 +669,7 @@ extern "C" int gs_solve_batch(const gs_plan_t* const* plans, int count, const vo
     };
     if (n_streams == 0 && ns_max > 1) {
         // trial: candidate stream counts, a few real rounds each
-        const int trial = std::min(3, opts->max_iter);
+        const int trial = std::min(std::max(3, ipg), opts->max_iter);
         double best = 1e300;
         int best_ns = ns_max;
         for (int cand = 1; cand <= ns_max && rounds + trial <= opts->max_iter && any_active(); cand *= 2) {
