@@ -856,13 +856,15 @@ hipError_t adjoint2d_tile_nb(const Plan& P, const cx<T>* u, cx<T>* x, int flags,
         GS_HIP_TRY(hipGetLastError());
     }
     // The interior and the column-side/corner kernels read the same staged
-    // input and write disjoint partials: the second runs on the plan's side
-    // stream, joined before the merges.  Under graph capture both stay on s.
+    // input and write disjoint partials.  FP64: the second runs on the plan's
+    // side stream, joined before the merges (the two long FP64 kernels overlap
+    // their tails: 8 % per pair).  FP32 gains nothing from it, so both stay on
+    // s, as they do under graph capture.
     hipStream_t s2 = s;
     if constexpr (NB > 0) {
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
         GS_HIP_TRY(hipStreamIsCapturing(s, &cap));
-        if (P.side && cap == hipStreamCaptureStatusNone) {
+        if (std::is_same<T, double>::value && P.side && cap == hipStreamCaptureStatusNone) {
             GS_HIP_TRY(hipEventRecord(P.ev_fork, s));
             GS_HIP_TRY(hipStreamWaitEvent(P.side, P.ev_fork, 0));
             s2 = P.side;
