@@ -33,9 +33,14 @@ def _case_1d(J, p, M, kind, seed):
     elif kind == "jitter":
         xi = jitter_1d(M, N / M * 2.0, seed)
         mu = voronoi_weights_1d(xi, np.abs(xi).max() + 0.5)
+    elif kind == "edges":  # grid nodes, band edges +-N, repeats
+        xi = 0.25 * rng.integers(-4 * N, 4 * N + 1, M).astype(float)
+        xi[:6] = [-N, N, 0.0, -0.0, N - 0.25, -N / 2]
+        xi[6:9] = xi[0]
+        mu = rng.uniform(0.1, 2.0, M)
     else:  # random, beyond the band and with repeated points
         xi = rng.uniform(-1.3 * N, 1.3 * N, M)
-        xi[:5] = xi[5]
+        xi[:5] = xi[min(5, M - 1)]
         mu = rng.uniform(0.1, 2.0, M)
     return xi, mu
 
@@ -49,6 +54,8 @@ ONE_D = [
     (9, 3, 1500, "random"),
     (12, 4, 6000, "jitter"),      # grid 8192 > LDS limit: four-step FFT
     (3, 4, 50, "random"),         # 2^J = 2p: no interior column
+    (7, 3, 900, "edges"),         # nodes, band edges, repeats
+    (6, 4, 1, "random"),          # a single point
 ]
 
 
@@ -86,6 +93,23 @@ def _case_2d(J, p, kind, M, seed):
     elif kind == "jitter":
         pts = jitter_2d(M, N / 2, seed)
         mu = voronoi_weights_2d(pts, "square", N / 2, N / np.sqrt(M))
+    elif kind == "cluster":
+        # every point within 0.2 of one frequency: one or two grid cells, one tile
+        # holding all M points (many staging chunks in one row block)
+        rng = np.random.default_rng(seed)
+        r = 0.2 * np.sqrt(rng.uniform(0, 1, M))
+        a = rng.uniform(0, 2 * np.pi, M)
+        pts = np.stack([0.37 * N + r * np.cos(a), -0.21 * N + r * np.sin(a)], axis=1)
+        mu = rng.uniform(0.5, 1.5, M)
+    elif kind == "edges":
+        # points on grid nodes (zero fractional position), on the band edges +-N
+        # (wrap to the same node as 0 in the oversampled grid) and a few repeats
+        rng = np.random.default_rng(seed)
+        k = rng.integers(-4 * N, 4 * N + 1, (M, 2))
+        pts = 0.25 * k.astype(float)
+        pts[:8] = [[-N, -N], [N, N], [-N, N], [N, -N], [0.0, -0.0], [-N / 2, N / 2], [N - 0.25, -N], [0.0, 0.0]]
+        pts[8:12] = pts[4]
+        mu = rng.uniform(0.5, 1.5, M)
     else:
         rng = np.random.default_rng(seed)
         pts = rng.uniform(-0.8 * N, 0.8 * N, (M, 2))
@@ -102,6 +126,10 @@ TWO_D = [
     (6, 4, "random", 5000),
     (7, 4, "random", 6000),       # 256^2 grid: two-pass register column transform (16 x 16)
     (8, 3, "spiral", 8000),       # 512^2 grid (32 x 16)
+    (6, 4, "cluster", 3000),      # all points in one tile
+    (5, 3, "edges", 1500),        # nodes, band edges, repeats
+    (6, 4, "random", 1),          # a single point
+    (7, 2, "random", 37),         # almost every tile empty
 ]
 
 
