@@ -72,7 +72,12 @@ typedef struct gs_plan gs_plan_t;
  * Freq2Wave, Sec. 6.2; its "init").
  *   out        receives the handle (freed with gs_destroy).
  *   dim        1 or 2.
- *   J          scale, N = 2^J coefficients per dimension; 1 <= J <= 13, 2^J >= 2p.
+ *   J          scale, N = 2^J coefficients per dimension; 2^J >= 2p and
+ *              1 <= J <= 20 (1D) or 11 (2D).  Plans holding FP32 data
+ *              (GS_F32, GS_F32_MIXED) need J <= 14: FP32 positions are 32-bit
+ *              fixed point with J + 1 bits of grid cell, and the window needs
+ *              17 bits of in-cell offset for FP32 accuracy (else
+ *              GS_ERR_UNSUPPORTED; GS_F64 plans cover the whole range).
  *   p          vanishing moments: 1 = Haar, 2..8 = Daubechies dbp with CDV
  *              boundary functions (App. A.1).
  *   M          number of samples, >= 1.

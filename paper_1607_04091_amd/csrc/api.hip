@@ -243,6 +243,8 @@ int gs_plan(gs_plan_t** out, int dim, int J, int p, int64_t M, const double* xi,
     if (p < 1 || p > 8) return GS_ERR_UNSUPPORTED;
     if (J < 1 || J > (dim == 2 ? 11 : 20)) return GS_ERR_UNSUPPORTED;
     if ((1 << J) < 2 * p) return GS_ERR_UNSUPPORTED;
+    // FP32 positions: 32-bit fixed point, J + 1 bits of cell, >= 17 bits of offset
+    if (precision != GS_F64 && J > 14) return GS_ERR_UNSUPPORTED;
     for (int64_t i = 0; i < M * dim; ++i)
         if (!std::isfinite(xi[i])) return GS_ERR_BAD_NODES;
     if (mu)

@@ -89,6 +89,10 @@ def test_plan_rejects_invalid_input_before_device_work():
     assert _plan_rc(J=2, p=4) == gs.GS_ERR_UNSUPPORTED          # 2^J < 2p
     assert _plan_rc(J=0, p=1) == gs.GS_ERR_UNSUPPORTED
     assert _plan_rc(dim=2, J=12, p=2) == gs.GS_ERR_UNSUPPORTED
+    assert _plan_rc(dim=1, J=21, p=2) == gs.GS_ERR_UNSUPPORTED
+    # FP32 data needs 17 bits of in-cell offset in a 32-bit position: J <= 14
+    assert _plan_rc(dim=1, J=15, p=2, prec=gs.GS_F32) == gs.GS_ERR_UNSUPPORTED
+    assert _plan_rc(dim=1, J=15, p=2, prec=gs.GS_F32_MIXED) == gs.GS_ERR_UNSUPPORTED
     bad = np.linspace(-10, 10, 10)
     bad[3] = np.nan
     assert _plan_rc(xi=bad) == gs.GS_ERR_BAD_NODES
