@@ -1,8 +1,9 @@
 """Full-size parity at the benchmark shape: 2D db4 at J = 9 (512 x 512
 coefficients), 1,048,576 Archimedean-spiral points (64 arms x 16384, radius
 256), mixed-precision plan, weighted operator, caller point order -- the
-launch configuration the benchmark times.  The FP64 oracle cannot form the
-full products at this size, so:
+launch configuration the benchmark times -- and at the warm-start workload's
+shape (J = 8, 256 x 256, 64 arms x 4096 points, radius 128).  The FP64
+oracle cannot form the full products at these sizes, so:
 
   * T x is compared on 128 sampled outputs, each row formed by the oracle;
   * T^H u is compared on 12 coefficients (boundary and interior indices) for
@@ -25,20 +26,21 @@ from gpu_util import rel, crandn, to_dev, to_host, say
 
 pytestmark = pytest.mark.gpu
 
-J, P = 9, 4
-N = 1 << J
+P = 4
+SHAPES = {"spiral_1M_J9": (9, 16384, 256.0), "spiral_262k_J8": (8, 4096, 128.0)}
 
 
-@pytest.fixture(scope="module")
-def setup():
+@pytest.fixture(scope="module", params=list(SHAPES))
+def setup(request):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1607_04091_amd import gs
-    pts = spiral_2d(64, 16384, 256.0, 0.5)
+    J, per_arm, r_max = SHAPES[request.param]
+    pts = spiral_2d(64, per_arm, r_max, 0.5)
     rng = np.random.default_rng(2024)
     mu = rng.uniform(0.5, 1.5, pts.shape[0])
     plan = gs.gs_plan(2, J, P, pts, mu, precision=gs.GS_F32_MIXED)
-    yield gs, plan, pts, mu
+    yield gs, plan, pts, mu, J
     plan.destroy()
 
 
@@ -48,7 +50,8 @@ def _dtype(f64):
 
 @pytest.mark.parametrize("f64", [True, False])
 def test_forward_sampled_rows(setup, f64):
-    gs, plan, pts, mu = setup
+    gs, plan, pts, mu, J = setup
+    N = 1 << J
     say(f"[fullsize T] M={pts.shape[0]} f64={f64}")
     rng = np.random.default_rng(11)
     X = crandn(rng, (N, N))
@@ -60,7 +63,8 @@ def test_forward_sampled_rows(setup, f64):
 
 @pytest.mark.parametrize("f64", [True, False])
 def test_adjoint_sampled_coefficients(setup, f64):
-    gs, plan, pts, mu = setup
+    gs, plan, pts, mu, J = setup
+    N = 1 << J
     say(f"[fullsize T^H] M={pts.shape[0]} f64={f64}")
     rng = np.random.default_rng(12)
     M = pts.shape[0]
@@ -69,14 +73,16 @@ def test_adjoint_sampled_coefficients(setup, f64):
     u[support] = crandn(rng, support.size)
     Z = to_host(plan.apply_TH(to_dev(u, _dtype(f64)), weighted=True, f64=f64))
     ij = np.array([[0, 0], [0, N - 1], [3, 4], [4, N // 2 - 1], [N // 2, N // 2 + 1], [N - 4, 3],
-                   [N - 1, N - 1], [100, 400], [N // 2, 7], [2, 300], [N - 3, N - 2], [130, 131]])
+                   [N - 1, N - 1], [N // 5, 4 * N // 5], [N // 2, 7], [2, 3 * N // 5], [N - 3, N - 2],
+                   [N // 4, N // 4 + 1]])
     want = basis.coeffs_TH_2d(pts[support], J, P, np.sqrt(mu[support]) * u[support], ij)
     assert rel(Z[ij[:, 0], ij[:, 1]], want) < (1e-12 if f64 else 2e-5)
 
 
 @pytest.mark.parametrize("f64", [True, False])
 def test_adjoint_identity_dense(setup, f64):
-    gs, plan, pts, mu = setup
+    gs, plan, pts, mu, J = setup
+    N = 1 << J
     say(f"[fullsize adjoint identity] f64={f64}")
     rng = np.random.default_rng(13)
     X = crandn(rng, (N, N))
