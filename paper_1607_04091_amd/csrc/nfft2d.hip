@@ -519,7 +519,7 @@ struct BndPre {
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 template <class T, int W, int DEG, int NB>
-__global__ void __launch_bounds__(BND_THREADS) adj_boundary_kernel(TileGeo<T> g, const cx<T>* __restrict__ vs,
+__global__ void __launch_bounds__(BND_THREADS) __attribute__((amdgpu_waves_per_eu(2))) adj_boundary_kernel(TileGeo<T> g, const cx<T>* __restrict__ vs,
                                                                    cx<T>* __restrict__ partC, cx<T>* __restrict__ partX) {
     using L = AdjBndLDS<T, W, NB>;
     constexpr int TS = TILE_TS, RB = ADJ_RB, PW = L::PW, NRB = L::NRB, NCH = L::NCH, NE = L::NE;
