@@ -175,3 +175,58 @@ def test_training_reduces_loss(gs):
     say(f"  loss {losses[0]:.3f} -> {losses[-1]:.4f}")
     assert losses[-1] < 0.2 * losses[0]
     net.destroy()
+
+
+def test_backward_complex128_target(gs):
+    """Targets given as complex128 (GS_CNN_TGT_F64) against the emulating oracle."""
+    say("[cnn bwd f64 target]")
+    B, H, W = 2, 18, 21
+    rng = np.random.default_rng(600)
+    w = _weights(6)
+    u = _c64(crandn(rng, (B, H, W)))
+    t = u + 0.3 * crandn(rng, (B, H, W))            # complex128, not rounded to FP32
+    net = gs.Cnn(H, W, B)
+    net.set_weights(w)
+    net.forward(to_dev(u, torch.complex64), train=True)
+    loss = net.backward(to_dev(t, torch.complex128))
+    ws = ocnn.unflatten(w.astype(np.float64))
+    out_e, cache_e = ocnn.forward(ws, u, emulate=True)
+    assert abs(loss - ocnn.loss(out_e, t)) <= 1e-3 * ocnn.loss(out_e, t)
+    ge = ocnn.backward(cache_e, out_e, t, emulate=True)
+    gg = ocnn.unflatten(net.get_grads().astype(np.float64))
+    for l in range(ocnn.N_LAYERS):
+        assert rel(gg[l], ge[l]) < 5e-3, l
+    net.destroy()
+
+
+def test_checkpoint_resume_is_exact(gs, tmp_path):
+    """Weights and Adam state saved after 3 steps and loaded into a new
+    handle continue training bit for bit like the original handle."""
+    say("[cnn checkpoint]")
+    B, H, W = 2, 24, 24
+    rng = np.random.default_rng(700)
+    u = to_dev(crandn(rng, (B, H, W)), torch.complex64)
+    t = to_dev(crandn(rng, (B, H, W)), torch.complex64)
+    a = gs.Cnn(H, W, B)
+    a.set_weights(_weights(7))
+    a.input_scale = 0.75
+    for _ in range(3):
+        a.forward(u, train=True)
+        a.backward(t, want_loss=False)
+        a.step(1e-3)
+    path = str(tmp_path / "ckpt.npz")
+    a.save(path)
+    b = gs.Cnn(H, W, B)
+    b.load(path)
+    assert b.input_scale == a.input_scale
+    for net in (a, b):
+        for _ in range(2):
+            net.forward(u, train=True)
+            net.backward(t, want_loss=False)
+            net.step(1e-3)
+    assert np.array_equal(a.get_weights(), b.get_weights())
+    ma, va, sa = a.get_state()
+    mb, vb, sb = b.get_state()
+    assert sa == sb == 5 and np.array_equal(ma, mb) and np.array_equal(va, vb)
+    a.destroy()
+    b.destroy()
