@@ -159,3 +159,24 @@ def test_cnn_argument_checks_without_gpu():
     assert lib.gs_cnn_step(None, 1e-3, 0.9, 0.999, 1e-8, None) == gs.GS_ERR_INVALID_ARG
     assert lib.gs_cnn_set_weights(None, None) == gs.GS_ERR_INVALID_ARG
     lib.gs_cnn_destroy(None)
+
+
+def test_plain_c_program_uses_the_abi(tmp_path):
+    """A C99 program written against include/gs.h compiles, links libgs.so and
+    runs its host-side checks (no GPU needed): the header is valid C and the
+    ABI is usable without Python."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    libdir = os.path.dirname(gs.LIB_PATH)
+    exe = str(tmp_path / "abi_check")
+    cmd = ["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(root, "include"),
+           os.path.join(root, "tests", "c", "abi_check.c"), "-L", libdir, "-lgs", "-lm",
+           f"-Wl,-rpath,{libdir}", "-Wl,-rpath-link,/opt/rocm/lib", "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "all C ABI checks passed" in r.stdout
