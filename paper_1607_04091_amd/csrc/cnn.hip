@@ -83,45 +83,56 @@ template <class TI>
 __global__ void __launch_bounds__(256) first_kernel(const TI* __restrict__ in, float scale, float* __restrict__ x0,
                                                     uint16_t* __restrict__ a1, const float* __restrict__ wq, int B,
                                                     int H, int W) {
-    __shared__ float sw[P1];
-    for (int i = threadIdx.x; i < P1; i += 256) sw[i] = wq[i];
-    __syncthreads();
+    // the workgroup's 256 x 64-byte output rows go through LDS so that each
+    // store instruction writes 1 KB of consecutive bytes
+    __shared__ uint4 so[256 * 5];   // row stride 5 x 16 B
     const int64_t n = (int64_t)B * H * W;
-    const int64_t pix = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (pix >= n) return;
-    const int x = (int)(pix % W);
-    const int y = (int)((pix / W) % H);
-    const int64_t b = pix / ((int64_t)W * H);
-    float acc[CH];
+    const int64_t pix0 = (int64_t)blockIdx.x * 256;
+    const int64_t pix = pix0 + threadIdx.x;
+    if (pix < n) {
+        const int x = (int)(pix % W);
+        const int y = (int)((pix / W) % H);
+        const int64_t b = pix / ((int64_t)W * H);
+        float acc[CH];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) acc[c] = 0.f;
-    for (int ky = 0; ky < 3; ++ky) {
-        const int yy = y + ky - 1;
-        if (yy < 0 || yy >= H) continue;
-        for (int kx = 0; kx < 3; ++kx) {
-            const int xx = x + kx - 1;
-            if (xx < 0 || xx >= W) continue;
-            const int64_t q = (b * H + yy) * W + xx;
-            const float v0 = (float)in[2 * q] * scale, v1 = (float)in[2 * q + 1] * scale;
-            const float* w = sw + (ky * 3 + kx) * 2 * CH;
+        for (int c = 0; c < CH; ++c) acc[c] = 0.f;
+        for (int ky = 0; ky < 3; ++ky) {
+            const int yy = y + ky - 1;
+            if (yy < 0 || yy >= H) continue;
+            for (int kx = 0; kx < 3; ++kx) {
+                const int xx = x + kx - 1;
+                if (xx < 0 || xx >= W) continue;
+                const int64_t q = (b * H + yy) * W + xx;
+                const float v0 = (float)in[2 * q] * scale, v1 = (float)in[2 * q + 1] * scale;
+                const float* w = wq + (ky * 3 + kx) * 2 * CH;   // wave-uniform: scalar loads
 #pragma unroll
-            for (int c = 0; c < CH; ++c) acc[c] = fmaf(v1, w[CH + c], fmaf(v0, w[c], acc[c]));
+                for (int c = 0; c < CH; ++c) acc[c] = fmaf(v1, w[CH + c], fmaf(v0, w[c], acc[c]));
+            }
+        }
+        x0[2 * pix] = (float)in[2 * pix] * scale;
+        x0[2 * pix + 1] = (float)in[2 * pix + 1] * scale;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float* a = acc + 8 * q;
+            so[threadIdx.x * 5 + q] =
+                make_uint4(pack2(fmaxf(a[0], 0.f), fmaxf(a[1], 0.f)), pack2(fmaxf(a[2], 0.f), fmaxf(a[3], 0.f)),
+                           pack2(fmaxf(a[4], 0.f), fmaxf(a[5], 0.f)), pack2(fmaxf(a[6], 0.f), fmaxf(a[7], 0.f)));
         }
     }
-    x0[2 * pix] = (float)in[2 * pix] * scale;
-    x0[2 * pix + 1] = (float)in[2 * pix + 1] * scale;
-    uint4* o = reinterpret_cast<uint4*>(a1 + pix * CH);
+    __syncthreads();
+    uint4* o = reinterpret_cast<uint4*>(a1 + pix0 * CH);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const float* a = acc + 8 * q;
-        o[q] = make_uint4(pack2(fmaxf(a[0], 0.f), fmaxf(a[1], 0.f)), pack2(fmaxf(a[2], 0.f), fmaxf(a[3], 0.f)),
-                          pack2(fmaxf(a[4], 0.f), fmaxf(a[5], 0.f)), pack2(fmaxf(a[6], 0.f), fmaxf(a[7], 0.f)));
+    for (int i = 0; i < 4; ++i) {
+        const int c = i * 256 + threadIdx.x, r = c >> 2;
+        if (pix0 + r < n) o[c] = so[r * 5 + (c & 3)];
     }
 }
 
 // ------------------------------------------------------------------ hidden 32 -> 32 convolution, MFMA
-// One workgroup = one 16 x 16 output tile of one image; the 18 x 18 x 32 input
-// tile (with halo, zero outside) is staged in LDS.  As a GEMM per tap t and
+// A workgroup takes 16 x 16 output tiles of one image in turn (tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ...); each 18 x 18 x 32 input tile (with
+// halo, zero outside) is staged in LDS, and the next tile's loads are issued
+// before the current tile is computed.  As a GEMM per tap t and
 // input-channel half h: D[co][pixel] += W_t[co][ci] X[ci][pixel]; A operands
 // (weights) come pre-packed per lane and stay in registers (36 fragments), B
 // operands (4 channels of one pixel, 8 bytes) are read from LDS.  Wave w owns
@@ -133,73 +144,92 @@ __global__ void __launch_bounds__(256) conv32_kernel(const uint16_t* __restrict_
                                                      int B, int H, int W, int tiles_x, int tiles_y) {
     __shared__ __align__(16) uint16_t tile[HALO * HALO * PSTR];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int t = blockIdx.x;
-    const int x0 = (t % tiles_x) * TS;
-    t /= tiles_x;
-    const int y0 = (t % tiles_y) * TS;
-    const int64_t b = t / tiles_y;
-
+    // the weight fragments are loaded once per workgroup; the workgroup then
+    // walks tiles blockIdx.x, blockIdx.x + gridDim.x, ...
     v4s wf[18][2];
 #pragma unroll
     for (int s = 0; s < 18; ++s)
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb) wf[s][mb] = as_v4s(wpack[(s * 2 + mb) * 64 + lane]);
-
-    for (int c = threadIdx.x; c < HALO * HALO * 4; c += 256) {
-        const int pl = c >> 2, part = c & 3;
-        const int py = pl / HALO, px = pl - py * HALO;
-        const int gy = y0 + py - 1, gx = x0 + px - 1;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-            v = *reinterpret_cast<const uint4*>(in + ((b * H + gy) * W + gx) * CH + part * 8);
-        uint2* d = reinterpret_cast<uint2*>(tile + pl * PSTR + part * 8);
-        d[0] = make_uint2(v.x, v.y);
-        d[1] = make_uint2(v.z, v.w);
-    }
-    __syncthreads();
-
-    v4f acc[4][2];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb) acc[r][mb] = v4f{0.f, 0.f, 0.f, 0.f};
     const int col = lane & 15, kq = lane >> 4;
+    const int ntiles = tiles_x * tiles_y * B;
+    constexpr int NLD = (HALO * HALO * 4 + 255) / 256;   // 16-byte loads per thread and tile
+    uint4 nx[NLD];
+    // loads of tile t's input (with halo) into registers; stored to LDS later,
+    // so that they are in flight while the previous tile is computed
+    auto fetch = [&](int t) {
+        const int x0 = (t % tiles_x) * TS, y0 = (t / tiles_x % tiles_y) * TS;
+        const int64_t b = t / tiles_x / tiles_y;
 #pragma unroll
-    for (int s = 0; s < 18; ++s) {
-        const int tap = s >> 1, h = s & 1, ky = tap / 3, kx = tap % 3;
+        for (int i = 0; i < NLD; ++i) {
+            const int c = threadIdx.x + 256 * i;
+            const int pl = c >> 2, part = c & 3;
+            const int py = pl / HALO, px = pl - py * HALO;
+            const int gy = y0 + py - 1, gx = x0 + px - 1;
+            nx[i] = make_uint4(0, 0, 0, 0);
+            if (c < HALO * HALO * 4 && gy >= 0 && gy < H && gx >= 0 && gx < W)
+                nx[i] = *reinterpret_cast<const uint4*>(in + ((b * H + gy) * W + gx) * CH + part * 8);
+        }
+    };
+    if ((int)blockIdx.x < ntiles) fetch(blockIdx.x);
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int x0 = (t % tiles_x) * TS, y0 = (t / tiles_x % tiles_y) * TS;
+        const int64_t b = t / tiles_x / tiles_y;
+        __syncthreads();   // the previous tile's reads of the LDS tile are done
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const int c = threadIdx.x + 256 * i;
+            if (c < HALO * HALO * 4) {
+                uint2* d = reinterpret_cast<uint2*>(tile + (c >> 2) * PSTR + (c & 3) * 8);
+                d[0] = make_uint2(nx[i].x, nx[i].y);
+                d[1] = make_uint2(nx[i].z, nx[i].w);
+            }
+        }
+        __syncthreads();
+        if (t + (int)gridDim.x < ntiles) fetch(t + gridDim.x);
+
+        v4f acc[4][2];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) acc[r][mb] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 18; ++s) {
+            const int tap = s >> 1, h = s & 1, ky = tap / 3, kx = tap % 3;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = wave * 4 + r;
+                const uint2 u =
+                    *reinterpret_cast<const uint2*>(tile + ((row + ky) * HALO + col + kx) * PSTR + h * 16 + kq * 4);
+                const v4s bv = as_v4s(u);
+                acc[r][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[s][0], bv, acc[r][0], 0, 0, 0);
+                acc[r][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[s][1], bv, acc[r][1], 0, 0, 0);
+            }
+        }
+        // lane holds D[co = 16 mb + 4 kq + j][pixel = col]
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int row = wave * 4 + r;
-            const uint2 u =
-                *reinterpret_cast<const uint2*>(tile + ((row + ky) * HALO + col + kx) * PSTR + h * 16 + kq * 4);
-            const v4s bv = as_v4s(u);
-            acc[r][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[s][0], bv, acc[r][0], 0, 0, 0);
-            acc[r][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[s][1], bv, acc[r][1], 0, 0, 0);
-        }
-    }
-    // lane holds D[co = 16 mb + 4 kq + j][pixel = col]
+            const int gy = y0 + wave * 4 + r, gx = x0 + col;
+            if (gy >= H || gx >= W) continue;
+            const int64_t pix = (b * H + gy) * W + gx;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int gy = y0 + wave * 4 + r, gx = x0 + col;
-        if (gy >= H || gx >= W) continue;
-        const int64_t pix = (b * H + gy) * W + gx;
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb) {
-            const int co = mb * 16 + kq * 4;
-            float v0 = acc[r][mb][0], v1 = acc[r][mb][1], v2 = acc[r][mb][2], v3 = acc[r][mb][3];
-            if (EPI == 0) {
-                v0 = fmaxf(v0, 0.f);
-                v1 = fmaxf(v1, 0.f);
-                v2 = fmaxf(v2, 0.f);
-                v3 = fmaxf(v3, 0.f);
-            } else {
-                const uint2 m = *reinterpret_cast<const uint2*>(mask + pix * CH + co);
-                v0 = bflo(m.x) > 0.f ? v0 : 0.f;
-                v1 = bfhi(m.x) > 0.f ? v1 : 0.f;
-                v2 = bflo(m.y) > 0.f ? v2 : 0.f;
-                v3 = bfhi(m.y) > 0.f ? v3 : 0.f;
+            for (int mb = 0; mb < 2; ++mb) {
+                const int co = mb * 16 + kq * 4;
+                float v0 = acc[r][mb][0], v1 = acc[r][mb][1], v2 = acc[r][mb][2], v3 = acc[r][mb][3];
+                if (EPI == 0) {
+                    v0 = fmaxf(v0, 0.f);
+                    v1 = fmaxf(v1, 0.f);
+                    v2 = fmaxf(v2, 0.f);
+                    v3 = fmaxf(v3, 0.f);
+                } else {
+                    const uint2 m = *reinterpret_cast<const uint2*>(mask + pix * CH + co);
+                    v0 = bflo(m.x) > 0.f ? v0 : 0.f;
+                    v1 = bfhi(m.x) > 0.f ? v1 : 0.f;
+                    v2 = bflo(m.y) > 0.f ? v2 : 0.f;
+                    v3 = bfhi(m.y) > 0.f ? v3 : 0.f;
+                }
+                *reinterpret_cast<uint2*>(out + pix * CH + co) = make_uint2(pack2(v0, v1), pack2(v2, v3));
             }
-            *reinterpret_cast<uint2*>(out + pix * CH + co) = make_uint2(pack2(v0, v1), pack2(v2, v3));
         }
     }
 }
@@ -209,16 +239,31 @@ __global__ void __launch_bounds__(256) conv32_kernel(const uint16_t* __restrict_
 template <class TO>
 __global__ void __launch_bounds__(256) last_kernel(const uint16_t* __restrict__ a5, const float* __restrict__ x0,
                                                    const float* __restrict__ wq, float* __restrict__ outf,
-                                                   TO* __restrict__ out, int B, int H, int W) {
-    __shared__ float sw[P6];
-    for (int i = threadIdx.x; i < P6; i += 256) sw[i] = wq[i];
+                                                   TO* __restrict__ out, int B, int H, int W, int tiles_x,
+                                                   int tiles_y) {
+    // one 16 x 16 pixel tile per workgroup; its 18 x 18 x 32 input (with halo,
+    // zero outside) is staged in LDS with coalesced loads
+    __shared__ __align__(16) uint16_t tile[HALO * HALO * PSTR];
+    int t = blockIdx.x;
+    const int tx0 = (t % tiles_x) * TS;
+    t /= tiles_x;
+    const int ty0 = (t % tiles_y) * TS;
+    const int64_t b = t / tiles_y;
+    for (int c = threadIdx.x; c < HALO * HALO * 4; c += 256) {
+        const int pl = c >> 2, part = c & 3;
+        const int py = pl / HALO, px = pl - py * HALO;
+        const int gy = ty0 + py - 1, gx = tx0 + px - 1;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+            v = *reinterpret_cast<const uint4*>(a5 + ((b * H + gy) * W + gx) * CH + part * 8);
+        uint2* d = reinterpret_cast<uint2*>(tile + pl * PSTR + part * 8);
+        d[0] = make_uint2(v.x, v.y);
+        d[1] = make_uint2(v.z, v.w);
+    }
     __syncthreads();
-    const int64_t n = (int64_t)B * H * W;
-    const int64_t pix = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (pix >= n) return;
-    const int x = (int)(pix % W);
-    const int y = (int)((pix / W) % H);
-    const int64_t b = pix / ((int64_t)W * H);
+    const int lx = threadIdx.x & 15, ly = threadIdx.x >> 4;
+    const int x = tx0 + lx, y = ty0 + ly;
+    if (x >= W || y >= H) return;
     float acc0 = 0.f, acc1 = 0.f;
     for (int ky = 0; ky < 3; ++ky) {
         const int yy = y + ky - 1;
@@ -226,15 +271,15 @@ __global__ void __launch_bounds__(256) last_kernel(const uint16_t* __restrict__ 
         for (int kx = 0; kx < 3; ++kx) {
             const int xx = x + kx - 1;
             if (xx < 0 || xx >= W) continue;
-            const uint4* p = reinterpret_cast<const uint4*>(a5 + ((b * H + yy) * W + xx) * CH);
-            const float* w = sw + (ky * 3 + kx) * CH * 2;
+            const uint16_t* p = tile + ((ly + ky) * HALO + lx + kx) * PSTR;
+            const float* w = wq + (ky * 3 + kx) * CH * 2;   // wave-uniform: scalar loads
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint4 v = p[q];
-                const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+            for (int q = 0; q < 8; ++q) {
+                const uint2 v = *reinterpret_cast<const uint2*>(p + 4 * q);
+                const uint32_t wd[2] = {v.x, v.y};
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int ci = 8 * q + 2 * e;
+                for (int e = 0; e < 2; ++e) {
+                    const int ci = 4 * q + 2 * e;
                     const float lo = bflo(wd[e]), hi = bfhi(wd[e]);
                     acc0 = fmaf(lo, w[2 * ci], acc0);
                     acc1 = fmaf(lo, w[2 * ci + 1], acc1);
@@ -244,6 +289,7 @@ __global__ void __launch_bounds__(256) last_kernel(const uint16_t* __restrict__ 
             }
         }
     }
+    const int64_t pix = (b * H + y) * W + x;
     const float o0 = x0[2 * pix] + acc0, o1 = x0[2 * pix + 1] + acc1;
     if (outf) {
         outf[2 * pix] = o0;
@@ -319,9 +365,6 @@ __global__ void __launch_bounds__(256) delta_out_kernel(const float* __restrict_
 __global__ void __launch_bounds__(256) last_bwd_kernel(const float* __restrict__ d6, const float* __restrict__ wq,
                                                        const uint16_t* __restrict__ a5, uint16_t* __restrict__ d5,
                                                        int B, int H, int W) {
-    __shared__ float sw[P6];
-    for (int i = threadIdx.x; i < P6; i += 256) sw[i] = wq[i];
-    __syncthreads();
     const int64_t n = (int64_t)B * H * W;
     const int64_t pix = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (pix >= n) return;
@@ -339,7 +382,7 @@ __global__ void __launch_bounds__(256) last_bwd_kernel(const float* __restrict__
             if (xx < 0 || xx >= W) continue;
             const int64_t q = (b * H + yy) * W + xx;
             const float e0 = d6[2 * q], e1 = d6[2 * q + 1];
-            const float* w = sw + (ky * 3 + kx) * CH * 2;
+            const float* w = wq + (ky * 3 + kx) * CH * 2;   // wave-uniform: scalar loads
 #pragma unroll
             for (int c = 0; c < CH; ++c) g[c] = fmaf(e1, w[2 * c + 1], fmaf(e0, w[2 * c], g[c]));
         }
@@ -581,11 +624,15 @@ struct Net {
     int step = 0;
     float in_scale = 1.f;      // fixed input scale (not trained)
     int train_batch = 0;       // batch of the last training forward (0: none)
+    int conv_wg = 512;         // workgroups of a convolution launch: two per compute unit
     std::vector<void*> allocs;
 };
 
 inline int64_t pix_count(const Net& n, int batch) { return (int64_t)batch * n.H * n.W; }
 inline int nblk(int64_t n, int t = 256) { return (int)std::max<int64_t>(1, (n + t - 1) / t); }
+// workgroups of the convolution kernels (each walks tiles, reusing its weight
+// fragments and prefetching the next tile): one resident round, two per CU
+inline int conv_grid(const Net& n, int tiles) { return std::min(tiles, n.conv_wg); }
 
 }  // namespace cnn
 }  // namespace gs
@@ -617,6 +664,12 @@ extern "C" int gs_cnn_create(gs_cnn_t** out, int height, int width, int max_batc
     n.H = height;
     n.W = width;
     n.maxB = max_batch;
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            n.conv_wg = 2 * cus;
+    }
     const int64_t np = (int64_t)max_batch * height * width;
     bool ok = true;
     auto alloc = [&](auto*& ptr, int64_t count) {
@@ -735,17 +788,17 @@ extern "C" int gs_cnn_forward(gs_cnn_t* c, const void* in, void* out, int batch,
     }
     for (int l = 0; l < 4; ++l) {
         ProfScope _p(K_CNN_CONV, st);
-        hipLaunchKernelGGL((conv32_kernel<0>), dim3(tiles), dim3(256), 0, st, n.act[l], n.fwd + l * PACK,
+        hipLaunchKernelGGL((conv32_kernel<0>), dim3(conv_grid(n, tiles)), dim3(256), 0, st, n.act[l], n.fwd + l * PACK,
                            n.act[l + 1], (const uint16_t*)nullptr, batch, n.H, n.W, tx, ty);
     }
     float* outf = (flags & GS_CNN_TRAIN) ? n.outf : nullptr;
     ProfScope _p(K_CNN_LAST, st);
     if (flags & GS_CNN_OUT_F64)
-        hipLaunchKernelGGL((last_kernel<double>), dim3(nblk(np)), dim3(256), 0, st, n.act[4], n.x0, n.wq6, outf,
-                           (double*)out, batch, n.H, n.W);
+        hipLaunchKernelGGL((last_kernel<double>), dim3(tiles), dim3(256), 0, st, n.act[4], n.x0, n.wq6, outf,
+                           (double*)out, batch, n.H, n.W, tx, ty);
     else
-        hipLaunchKernelGGL((last_kernel<float>), dim3(nblk(np)), dim3(256), 0, st, n.act[4], n.x0, n.wq6, outf,
-                           (float*)out, batch, n.H, n.W);
+        hipLaunchKernelGGL((last_kernel<float>), dim3(tiles), dim3(256), 0, st, n.act[4], n.x0, n.wq6, outf,
+                           (float*)out, batch, n.H, n.W, tx, ty);
     if (hipGetLastError() != hipSuccess) return GS_ERR_HIP;
     n.train_batch = (flags & GS_CNN_TRAIN) ? batch : 0;
     return GS_OK;
@@ -808,7 +861,7 @@ extern "C" int gs_cnn_backward(gs_cnn_t* c, const void* target, int batch, int f
             reduce(dw_wg, PH, n.g + poff(l - 1));
         }
         ProfScope _p(K_CNN_CONV_BWD, st);
-        hipLaunchKernelGGL((conv32_kernel<1>), dim3(tiles), dim3(256), 0, st, n.dl[cur], n.bwd + (l - 2) * PACK,
+        hipLaunchKernelGGL((conv32_kernel<1>), dim3(conv_grid(n, tiles)), dim3(256), 0, st, n.dl[cur], n.bwd + (l - 2) * PACK,
                            n.dl[cur ^ 1], a_prev, batch, n.H, n.W, tx, ty);
         cur ^= 1;
     }
