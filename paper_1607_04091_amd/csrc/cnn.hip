@@ -410,7 +410,8 @@ __global__ void __launch_bounds__(256) last_bwd_kernel(const float* __restrict__
 // so that a lane's 4 consecutive pixels are one 8-byte read; the activation
 // tile is kept in three copies shifted by kx = 0, 1, 2 so every read is
 // aligned.  Wave w owns (co block w >> 1, ci block w & 1) for all 9 taps.
-// Workgroups loop over tiles; each writes one FP32 partial of all 9216
+// Workgroups loop over tiles, issuing the next tile's global loads before
+// computing the current one; each writes one FP32 partial of all 9216
 // gradients, summed afterwards in a fixed order.
 __global__ void __launch_bounds__(256) dw32_kernel(const uint16_t* __restrict__ act, const uint16_t* __restrict__ dlt,
                                                    float* __restrict__ part, int B, int H, int W, int tiles_x,
@@ -424,34 +425,56 @@ __global__ void __launch_bounds__(256) dw32_kernel(const uint16_t* __restrict__ 
 #pragma unroll
     for (int t = 0; t < TAPS; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
     const int64_t ntiles = (int64_t)tiles_x * tiles_y * B;
+    constexpr int NDL = TS * TS * 4 / 256, NAL = (HALO * HALO * 4 + 255) / 256;   // 16-byte loads per thread
+    static_assert(TS * TS * 4 % 256 == 0, "whole d-tile loads");
+    uint4 nd[NDL], na[NAL];
+    // loads of tile tl's d values and activations (with halo) into registers;
+    // stored to LDS later, so that they are in flight while the previous tile
+    // is computed
+    auto fetch = [&](int64_t tl) {
+        const int x0 = (int)(tl % tiles_x) * TS, y0 = (int)(tl / tiles_x % tiles_y) * TS;
+        const int64_t b = tl / tiles_x / tiles_y;
+#pragma unroll
+        for (int i = 0; i < NDL; ++i) {
+            const int c = threadIdx.x + 256 * i;
+            const int pl = c >> 2, part8 = (c & 3) * 8;
+            const int gy = y0 + (pl >> 4), gx = x0 + (pl & 15);
+            nd[i] = make_uint4(0, 0, 0, 0);
+            if (gy < H && gx < W) nd[i] = *reinterpret_cast<const uint4*>(dlt + ((b * H + gy) * W + gx) * CH + part8);
+        }
+#pragma unroll
+        for (int i = 0; i < NAL; ++i) {
+            const int c = threadIdx.x + 256 * i;
+            const int pl = c >> 2, part8 = (c & 3) * 8;
+            const int py = pl / HALO, px = pl - py * HALO;
+            const int gy = y0 + py - 1, gx = x0 + px - 1;
+            na[i] = make_uint4(0, 0, 0, 0);
+            if (c < HALO * HALO * 4 && gy >= 0 && gy < H && gx >= 0 && gx < W)
+                na[i] = *reinterpret_cast<const uint4*>(act + ((b * H + gy) * W + gx) * CH + part8);
+        }
+    };
+    if ((int64_t)blockIdx.x < ntiles) fetch(blockIdx.x);
     for (int64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
-        int64_t t = tl;
-        const int x0 = (int)(t % tiles_x) * TS;
-        t /= tiles_x;
-        const int y0 = (int)(t % tiles_y) * TS;
-        const int64_t b = t / tiles_y;
-        __syncthreads();
-        for (int c = threadIdx.x; c < TS * TS * 4; c += 256) {
+        __syncthreads();   // the previous tile's reads of Dt and As are done
+#pragma unroll
+        for (int i = 0; i < NDL; ++i) {
+            const int c = threadIdx.x + 256 * i;
             const int pl = c >> 2, part8 = (c & 3) * 8;
             const int ry = pl >> 4, rx = pl & 15;
-            const int gy = y0 + ry, gx = x0 + rx;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (gy < H && gx < W) v = *reinterpret_cast<const uint4*>(dlt + ((b * H + gy) * W + gx) * CH + part8);
-            const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+            const uint32_t w4[4] = {nd[i].x, nd[i].y, nd[i].z, nd[i].w};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 Dt[(part8 + 2 * e) * DSTR + ry * TS + rx] = (uint16_t)(w4[e] & 0xFFFF);
                 Dt[(part8 + 2 * e + 1) * DSTR + ry * TS + rx] = (uint16_t)(w4[e] >> 16);
             }
         }
-        for (int c = threadIdx.x; c < HALO * HALO * 4; c += 256) {
+#pragma unroll
+        for (int i = 0; i < NAL; ++i) {
+            const int c = threadIdx.x + 256 * i;
+            if (c >= HALO * HALO * 4) continue;
             const int pl = c >> 2, part8 = (c & 3) * 8;
             const int py = pl / HALO, px = pl - py * HALO;
-            const int gy = y0 + py - 1, gx = x0 + px - 1;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-                v = *reinterpret_cast<const uint4*>(act + ((b * H + gy) * W + gx) * CH + part8);
-            const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+            const uint32_t w4[4] = {na[i].x, na[i].y, na[i].z, na[i].w};
 #pragma unroll
             for (int s = 0; s < 3; ++s) {
                 const int xp = px - s;
@@ -464,6 +487,7 @@ __global__ void __launch_bounds__(256) dw32_kernel(const uint16_t* __restrict__ 
             }
         }
         __syncthreads();
+        if (tl + gridDim.x < ntiles) fetch(tl + gridDim.x);
         for (int rho = 0; rho < TS; ++rho) {
             const v4s av = as_v4s(*reinterpret_cast<const uint2*>(Dt + (16 * mb + c16) * DSTR + rho * TS + 4 * kq));
 #pragma unroll
@@ -484,57 +508,84 @@ __global__ void __launch_bounds__(256) dw32_kernel(const uint16_t* __restrict__ 
 }
 
 // ------------------------------------------------------------------ thin-layer weight gradients, ALU
-// dW[t][cu][cv] = sum_p U[p + t][cu] V[p][cv] with CU * CV = 64: lane (cu, cv)
-// of a wave owns the 9 taps of one (cu, cv) pair.  A wave walks row segments in
-// chunks of THIN_CH pixels: it loads the chunk's 3 x (THIN_CH + 2) values of U
-// and THIN_CH values of V into registers at once (lanes sharing cu or cv read
-// the same addresses), then does the 9 THIN_CH FMAs.  The four waves of a
-// workgroup add their sums in LDS in a fixed order; one partial per workgroup.
-constexpr int THIN_CH = 16;
+// dW[t][cu][cv] = sum_p U[p + t][cu] V[p][cv] with CU * CV = 64.  A workgroup
+// takes row segments of THIN_SEG pixels in turn.  It stages the segment's three
+// input rows of U (one extra pixel either side, zero outside the image) and its
+// V values in LDS with 16- or 8-byte loads, then wave w sums pixels
+// THIN_CH w .. THIN_CH w + THIN_CH - 1 of the segment: lane (cu, cv) owns the 9
+// taps of one (cu, cv) pair and reads the 3 x (THIN_CH + 2) values of U and the
+// THIN_CH values of V it needs into registers.  The four waves add their sums in
+// LDS in a fixed order; one partial per workgroup.
+constexpr int THIN_CH = THIN_SEG / 4;
+template <int NB> struct VecOf;
+template <> struct VecOf<16> {
+    using type = uint4;
+    __device__ static type zero() { return make_uint4(0, 0, 0, 0); }
+};
+template <> struct VecOf<8> {
+    using type = uint2;
+    __device__ static type zero() { return make_uint2(0, 0); }
+};
+
 template <int CU, int CV, class UT, class VT>
 __global__ void __launch_bounds__(256) dw_thin_kernel(const UT* __restrict__ U, const VT* __restrict__ V,
                                                       float* __restrict__ part, int B, int H, int W, int segs_x) {
     static_assert(CU * CV == 64, "one (cu, cv) pair per lane");
+    constexpr int UPX = CU * (int)sizeof(UT), VPX = CV * (int)sizeof(VT);     // bytes per pixel
+    constexpr int UVB = UPX >= 16 ? 16 : UPX, VVB = VPX >= 16 ? 16 : VPX;       // bytes per load
+    static_assert(UPX % UVB == 0 && VPX % VVB == 0 && (UVB == 16 || UVB == 8) && (VVB == 16 || VVB == 8),
+                  "pixel rows load as whole 8- or 16-byte vectors");
+    using UVec = typename VecOf<UVB>::type;
+    using VVec = typename VecOf<VVB>::type;
+    constexpr int SEGU = THIN_SEG + 2;
+    __shared__ __align__(16) unsigned char su[3 * SEGU * UPX];
+    __shared__ __align__(16) unsigned char sv[THIN_SEG * VPX];
     __shared__ float red[4][TAPS * 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int cu = lane / CV, cv = lane % CV;
+    const UT* lu = reinterpret_cast<const UT*>(su);
+    const VT* lv = reinterpret_cast<const VT*>(sv);
     const int64_t nseg = (int64_t)B * H * segs_x;
     float acc[TAPS];
 #pragma unroll
     for (int t = 0; t < TAPS; ++t) acc[t] = 0.f;
-    for (int64_t sg = (int64_t)blockIdx.x * 4 + wave; sg < nseg; sg += (int64_t)gridDim.x * 4) {
+    for (int64_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
         const int sx = (int)(sg % segs_x);
         const int y = (int)((sg / segs_x) % H);
         const int64_t b = sg / ((int64_t)segs_x * H);
         const int x0 = sx * THIN_SEG;
-        const int x1 = min(W, x0 + THIN_SEG);
-        bool rowok[3];
-        int64_t rowbase[3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const int yy = y + r - 1;
-            rowok[r] = yy >= 0 && yy < H;
-            rowbase[r] = (b * H + (rowok[r] ? yy : 0)) * (int64_t)W;
+        __syncthreads();   // the previous segment's reads of su and sv are done
+        constexpr int UPV = UPX / UVB, VPV = VPX / VVB;   // loads per pixel
+        for (int c = threadIdx.x; c < 3 * SEGU * UPV; c += 256) {
+            const int r = c / (SEGU * UPV), px = (c / UPV) % SEGU, k = c % UPV;
+            const int yy = y + r - 1, x = x0 - 1 + px;
+            UVec v = VecOf<UVB>::zero();
+            if (yy >= 0 && yy < H && x >= 0 && x < W)
+                v = reinterpret_cast<const UVec*>(U + ((b * H + yy) * W + x) * CU)[k];
+            reinterpret_cast<UVec*>(su)[c] = v;
         }
-        const int64_t vbase = (b * H + y) * (int64_t)W;
-        for (int xc = x0; xc < x1; xc += THIN_CH) {
-            float u[3][THIN_CH + 2], v[THIN_CH];
+        for (int c = threadIdx.x; c < THIN_SEG * VPV; c += 256) {
+            const int px = c / VPV, k = c % VPV;
+            const int x = x0 + px;
+            VVec v = VecOf<VVB>::zero();
+            if (x < W) v = reinterpret_cast<const VVec*>(V + ((b * H + y) * W + x) * CV)[k];
+            reinterpret_cast<VVec*>(sv)[c] = v;
+        }
+        __syncthreads();
+        const int k0 = wave * THIN_CH;
+        float u[3][THIN_CH + 2], v[THIN_CH];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int k = 0; k < THIN_CH + 2; ++k) u[r][k] = ldv(lu, (r * SEGU + k0 + k) * CU + cu);
+#pragma unroll
+        for (int k = 0; k < THIN_CH; ++k) v[k] = ldv(lv, (k0 + k) * CV + cv);
+#pragma unroll
+        for (int k = 0; k < THIN_CH; ++k)
 #pragma unroll
             for (int r = 0; r < 3; ++r)
 #pragma unroll
-                for (int k = 0; k < THIN_CH + 2; ++k) {
-                    const int x = xc - 1 + k;
-                    u[r][k] = (rowok[r] && x >= 0 && x < W) ? ldv(U, (rowbase[r] + x) * CU + cu) : 0.f;
-                }
-#pragma unroll
-            for (int k = 0; k < THIN_CH; ++k) v[k] = (xc + k < W) ? ldv(V, (vbase + xc + k) * CV + cv) : 0.f;
-#pragma unroll
-            for (int k = 0; k < THIN_CH; ++k)
-#pragma unroll
-                for (int r = 0; r < 3; ++r)
-#pragma unroll
-                    for (int kx = 0; kx < 3; ++kx) acc[r * 3 + kx] = fmaf(u[r][k + kx], v[k], acc[r * 3 + kx]);
-        }
+                for (int kx = 0; kx < 3; ++kx) acc[r * 3 + kx] = fmaf(u[r][k + kx], v[k], acc[r * 3 + kx]);
     }
 #pragma unroll
     for (int t = 0; t < TAPS; ++t) red[wave][t * 64 + lane] = acc[t];
@@ -815,7 +866,7 @@ extern "C" int gs_cnn_backward(gs_cnn_t* c, const void* target, int batch, int f
     const int tiles = tx * ty * batch;
     const int dw_wg = std::min(DW_WG, tiles);
     const int segs_x = (n.W + THIN_SEG - 1) / THIN_SEG;
-    const int thin_wg = (int)std::min<int64_t>(THIN_WG, ((int64_t)batch * n.H * segs_x + 3) / 4);
+    const int thin_wg = (int)std::min<int64_t>(THIN_WG, (int64_t)batch * n.H * segs_x);
     auto reduce = [&](int nparts, int count, float* out) {
         hipLaunchKernelGGL(dw_reduce1_kernel, dim3(nblk(count), RED_G), dim3(256), 0, st, n.part, nparts, count,
                            n.red);
