@@ -13,8 +13,11 @@ plain FP64.  Tolerances (norm-wise relative):
     a handful of pixels these do not average out;
   * Adam step: <= 1e-5 of the weights (FP32 against FP64 arithmetic).
 Shapes cover one tile, ragged tiles (sides not multiples of 16), a single
-row, several images, and the full 256 x 256 images of the warm-start
-workload."""
+row, several images, the full 256 x 256 images of the warm-start workload,
+and 40 ragged 80 x 72 images: 1000 tiles, more than the convolution and
+weight-gradient kernels have workgroups (two per CU), so workgroups walk
+several tiles across image borders with the next tile's loads in flight, and
+2560 row segments for the thin-layer gradient's 1024 workgroups."""
 import numpy as np
 import pytest
 
@@ -49,7 +52,7 @@ def _c64(a):
     return np.asarray(a).astype(np.complex64).astype(np.complex128)
 
 
-SHAPES = [(1, 16, 16), (2, 20, 37), (3, 33, 17), (1, 1, 5), (2, 256, 256)]
+SHAPES = [(1, 16, 16), (2, 20, 37), (3, 33, 17), (1, 1, 5), (2, 256, 256), (40, 80, 72)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
