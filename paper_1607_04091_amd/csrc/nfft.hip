@@ -446,14 +446,28 @@ __global__ void __launch_bounds__(256) boundary_partial_kernel(Geo<T> g, const c
     }
 }
 
+// One wave per (r, c) output: lane l sums partials l, l + 64, ... in order,
+// then a fixed butterfly over the 64 lanes.
 template <class T>
-__global__ void boundary_final_kernel(Geo<T> g, const cx<T>* __restrict__ part, int nblk, cx<T>* __restrict__ X) {
+__global__ void __launch_bounds__(64) boundary_final_kernel(Geo<T> g, const cx<T>* __restrict__ part, int nblk,
+                                                            cx<T>* __restrict__ X) {
     const int nch = 2 * g.nb;
     const int npairs = g.dim == 2 ? nch * nch : nch;
-    const int i = threadIdx.x;
+    const int i = blockIdx.x;
     if (i >= npairs) return;
-    cx<T> s = czero<T>();
-    for (int b = 0; b < nblk; ++b) s = cadd(s, part[(size_t)b * npairs + i]);
+    T sx = T(0), sy = T(0);
+    for (int b = threadIdx.x; b < nblk; b += 64) {
+        const cx<T> v = part[(size_t)b * npairs + i];
+        sx += v.x;
+        sy += v.y;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        sx += __shfl_xor(sx, off);
+        sy += __shfl_xor(sy, off);
+    }
+    if (threadIdx.x != 0) return;
+    const cx<T> s = mk<T>(sx, sy);
     if (g.dim == 2) X[(size_t)g.bcol(i / nch) * g.N + g.bcol(i % nch)] = s;
     else X[g.bcol(i)] = s;
 }
@@ -479,7 +493,9 @@ __global__ void __launch_bounds__(256) spread1d_kernel(Geo<T> g, const cx<T>* __
 // ------------------------------------------------------------------ launchers
 
 inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
-constexpr int BOUNDARY_CHUNK = 4096;
+// workgroups of the boundary-block reduction: about 512 points each, at most
+// 256 (the final kernel sums their partials in order)
+inline int boundary_blocks(int64_t M) { return (int)std::min<int64_t>(256, std::max<int64_t>(1, (M + 511) / 512)); }
 
 template <class T> struct WinParams;
 template <> struct WinParams<float> { static constexpr int W = W32, DEG = DEG32; };
@@ -605,13 +621,14 @@ hipError_t launch_apply_TH(const Plan& P, const cx<T>* u, cx<T>* x, int flags, h
     GS_TIMED(K_ADJ_PREP, hipLaunchKernelGGL((adj_prep_kernel<T>), dim3(nblk(P.M, 256)), dim3(256), 0, s, g, u, v, vI,
                                             flags));
     GS_HIP_TRY(hipGetLastError());
-    const int nbl = nblk(P.M, BOUNDARY_CHUNK);
+    const int nbl = boundary_blocks(P.M);
     if (nb) {
         GS_TIMED(K_BOUNDARY_PARTIAL, hipLaunchKernelGGL((boundary_partial_kernel<T>), dim3(nbl), dim3(256), 0, s, g, v,
-                                                        part, BOUNDARY_CHUNK));
+                                                        part, (int)((P.M + nbl - 1) / nbl)));
         GS_HIP_TRY(hipGetLastError());
         GS_TIMED(K_BOUNDARY_FINAL,
-                 hipLaunchKernelGGL((boundary_final_kernel<T>), dim3(1), dim3(256), 0, s, g, part, nbl, x));
+                 hipLaunchKernelGGL((boundary_final_kernel<T>), dim3(P.dim == 2 ? 4 * nb * nb : 2 * nb), dim3(64), 0, s,
+                                    g, part, nbl, x));
         GS_HIP_TRY(hipGetLastError());
     }
     if (P.dim == 2) {
@@ -670,7 +687,7 @@ template hipError_t launch_apply_TH<double>(const Plan&, const cx<double>*, cx<d
 // partial-buffer size needed by the adjoint (elements)
 size_t adjoint_part_elems(int dim, int64_t M, int nb, int ng) {
     size_t need = (size_t)M;  // vI
-    size_t b = (size_t)((M + BOUNDARY_CHUNK - 1) / BOUNDARY_CHUNK) * (size_t)(dim == 2 ? 4 * nb * nb : 2 * nb);
+    size_t b = (size_t)boundary_blocks(M) * (size_t)(dim == 2 ? 4 * nb * nb : 2 * nb);
     size_t sides = 0;
     if (dim == 2 && nb) {
         const int strip = std::min(ng, 64);
