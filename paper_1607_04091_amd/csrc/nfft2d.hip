@@ -83,6 +83,12 @@ __device__ inline void taps_all(T t, const T* __restrict__ coef, T* w) {
 
 constexpr int TILE_TS = 32;     // grid cells per tile side
 constexpr int TILE_RB = 8;      // cell rows per column-owner block
+// threads of the forward tile kernels, which loop over the tile's points: one
+// point per thread on average in FP32, so that grids of few tiles (one
+// workgroup per CU) still keep 16 waves per CU; FP64 keeps 256, its
+// registers (up to 126) would not fit 1024-thread workgroups
+template <class T> struct FwdThreads { static constexpr int value = 256; };
+template <> struct FwdThreads<float> { static constexpr int value = 1024; };
 
 // ------------------------------------------------------------------ forward
 
@@ -90,7 +96,7 @@ constexpr int TILE_RB = 8;      // cell rows per column-owner block
 // present, computed beforehand in sorted order), scales, weights and the
 // scatter to caller order.
 template <class T, int W, int DEG, bool BND>
-__global__ void __launch_bounds__(256) interp_tile_kernel(TileGeo<T> g, const cx<T>* __restrict__ grid,
+__global__ void __launch_bounds__(FwdThreads<T>::value) interp_tile_kernel(TileGeo<T> g, const cx<T>* __restrict__ grid,
                                                           const cx<T>* __restrict__ ybnd, cx<T>* __restrict__ y,
                                                           int flags) {
     constexpr int TS = TILE_TS, PW = TS + W - 1;
@@ -139,7 +145,7 @@ __global__ void __launch_bounds__(256) interp_tile_kernel(TileGeo<T> g, const cx
 // S_r the 1D interpolation (along y) of the row-side grid r and C_c that of the
 // column-side grid c (along x).  Written in sorted order; the interior kernel adds it.
 template <class T, int W, int DEG, int NB>
-__global__ void __launch_bounds__(256) interp_bnd_kernel(TileGeo<T> g, const cx<T>* __restrict__ sr,
+__global__ void __launch_bounds__(FwdThreads<T>::value) interp_bnd_kernel(TileGeo<T> g, const cx<T>* __restrict__ sr,
                                                          const cx<T>* __restrict__ sc, const cx<T>* __restrict__ X,
                                                          cx<T>* __restrict__ ybnd) {
     constexpr int TS = TILE_TS, PW = TS + W - 1, NCH = 2 * NB;
@@ -828,13 +834,13 @@ hipError_t interp2d_tile_nb(const Plan& P, const cx<T>* x, cx<T>* y, int flags, 
     const int nt = g.ntx * g.ntx;
     if constexpr (NB > 0) {
         ProfScope _p(K_INTERP_BND, s);
-        hipLaunchKernelGGL((interp_bnd_kernel<T, W, DEG, NB>), dim3(nt), dim3(256), 0, s, g, (const cx<T>*)d.sr,
-                           (const cx<T>*)d.sc, x, d.ybuf);
+        hipLaunchKernelGGL((interp_bnd_kernel<T, W, DEG, NB>), dim3(nt), dim3(FwdThreads<T>::value), 0, s, g,
+                           (const cx<T>*)d.sr, (const cx<T>*)d.sc, x, d.ybuf);
         GS_HIP_TRY(hipGetLastError());
     }
     ProfScope _p(K_INTERP2D, s);
-    hipLaunchKernelGGL((interp_tile_kernel<T, W, DEG, (NB > 0)>), dim3(nt), dim3(256), 0, s, g, (const cx<T>*)d.grid,
-                       (const cx<T>*)d.ybuf, y, flags);
+    hipLaunchKernelGGL((interp_tile_kernel<T, W, DEG, (NB > 0)>), dim3(nt), dim3(FwdThreads<T>::value), 0, s, g,
+                       (const cx<T>*)d.grid, (const cx<T>*)d.ybuf, y, flags);
     return hipGetLastError();
 }
 
@@ -856,15 +862,17 @@ hipError_t adjoint2d_tile_nb(const Plan& P, const cx<T>* u, cx<T>* x, int flags,
         GS_HIP_TRY(hipGetLastError());
     }
     // The interior and the column-side/corner kernels read the same staged
-    // input and write disjoint partials.  FP64: the second runs on the plan's
-    // side stream, joined before the merges (the two long FP64 kernels overlap
-    // their tails: 8 % per pair).  FP32 gains nothing from it, so both stay on
-    // s, as they do under graph capture.
+    // input and write disjoint partials.  The second runs on the plan's side
+    // stream, joined before the merges, in FP64 (the two long FP64 kernels
+    // overlap their tails: 8 % per pair) and in FP32 on grids of at most 256
+    // tiles, where each kernel alone has one workgroup per CU (the pair of the
+    // 262,144-point J = 8 workload: 147 -> 137 us).  On larger FP32 grids each
+    // kernel fills the chip and both stay on s, as they do under graph capture.
     hipStream_t s2 = s;
     if constexpr (NB > 0) {
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
         GS_HIP_TRY(hipStreamIsCapturing(s, &cap));
-        if (std::is_same<T, double>::value && P.side && cap == hipStreamCaptureStatusNone) {
+        if ((std::is_same<T, double>::value || nt <= 256) && P.side && cap == hipStreamCaptureStatusNone) {
             GS_HIP_TRY(hipEventRecord(P.ev_fork, s));
             GS_HIP_TRY(hipStreamWaitEvent(P.side, P.ev_fork, 0));
             s2 = P.side;
