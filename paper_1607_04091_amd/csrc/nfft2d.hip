@@ -489,12 +489,18 @@ __global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(Tile
 //     work is balanced whatever the distribution of points,
 //   * runs a quarter of the corner products sum_m conj(ax_r ay_c) sqrt(mu_m) u_m
 //     as real 16x16x4 MFMA steps over the chunk's slots.
-// Workgroups of four wavefronts run two per CU with up to 80 KB of LDS each.
+// Workgroups of four wavefronts run two per CU with up to 80 KB of LDS each,
+// four per CU with up to 40 KB.  The stage budget is a template parameter:
+// FP32 on grids of more than 256 tiles stages 12 points per row block (about
+// 40 KB, four workgroups per CU: 73 against 78 us with the 76 KB stage at the
+// 1,048,576-point J = 9 workload); on smaller grids, where the kernel runs
+// beside the interior kernel, and in FP64 the stage fills 76 KB.
 constexpr int BND_WAVES = 4;
 constexpr int BND_THREADS = 64 * BND_WAVES;
 constexpr int BND_LDS = 76 * 1024;
+constexpr int BND_LDS_FOUR = 40 * 1024;
 
-template <class T, int W, int NB>
+template <class T, int W, int NB, int BL = BND_LDS>
 struct AdjBndLDS {
     static constexpr int TS = TILE_TS, PW = TS + W - 1, NRB = TS / ADJ_RB;
     static constexpr int NCH = 2 * NB, NE = 4 * NB;          // channels; real entries of e, f
@@ -503,7 +509,7 @@ struct AdjBndLDS {
     static constexpr int FIXED = (int)(4 * (TS * TS + 1) + BND_WAVES * NCH * PW * sizeof(cx<T>) +
                                        BND_WAVES * LD * LD * sizeof(T));
     static constexpr int SLOT = (int)(W * sizeof(T) + NCH * sizeof(cx<T>) + 2 * NE * sizeof(T));
-    static constexpr int CHB = adj_chb(BND_LDS - FIXED, SLOT, NRB, 4, 32, 4), CH = NRB * CHB;
+    static constexpr int CHB = adj_chb(BL - FIXED, SLOT, NRB, 4, 32, 4), CH = NRB * CHB;
     struct Stage {
         T wx[CH][W];
         cx<T> dc[CH][NCH];   // conj(ay_c Dx) sqrt(mu) u: column-side values
@@ -524,10 +530,10 @@ struct BndPre {
 
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-template <class T, int W, int DEG, int NB>
+template <class T, int W, int DEG, int NB, int BL>
 __global__ void __launch_bounds__(BND_THREADS) __attribute__((amdgpu_waves_per_eu(2))) adj_boundary_kernel(TileGeo<T> g, const cx<T>* __restrict__ vs,
                                                                    cx<T>* __restrict__ partC, cx<T>* __restrict__ partX) {
-    using L = AdjBndLDS<T, W, NB>;
+    using L = AdjBndLDS<T, W, NB, BL>;
     constexpr int TS = TILE_TS, RB = ADJ_RB, PW = L::PW, NRB = L::NRB, NCH = L::NCH, NE = L::NE;
     constexpr int CH = L::CH, CHB = L::CHB;
     constexpr int NBLK = L::NBLK, LD = L::LD;
@@ -878,8 +884,12 @@ hipError_t adjoint2d_tile_nb(const Plan& P, const cx<T>* u, cx<T>* x, int flags,
             s2 = P.side;
         }
         ProfScope _p(K_BND2D, s2);
-        hipLaunchKernelGGL((adj_boundary_kernel<T, W, DEG, NB>), dim3(nt), dim3(BND_THREADS), 0, s2, g,
-                           (const cx<T>*)d.vbuf, partC, partX);
+        if (std::is_same<T, float>::value && nt > 256)
+            hipLaunchKernelGGL((adj_boundary_kernel<T, W, DEG, NB, std::is_same<T, float>::value ? BND_LDS_FOUR : BND_LDS>),
+                               dim3(nt), dim3(BND_THREADS), 0, s2, g, (const cx<T>*)d.vbuf, partC, partX);
+        else
+            hipLaunchKernelGGL((adj_boundary_kernel<T, W, DEG, NB, BND_LDS>), dim3(nt), dim3(BND_THREADS), 0, s2, g,
+                               (const cx<T>*)d.vbuf, partC, partX);
         GS_HIP_TRY(hipGetLastError());
     }
     {
