@@ -47,6 +47,73 @@ def test_filter_invariants(p):
         assert abs(h[0]) > abs(h[-1])
 
 
+def test_db4_taps_textbook_table():
+    """db4 (p = 4) against Daubechies' published extremal-phase table (Ten
+    Lectures, Table 6.1, N = 4), which fixes the phase family that the
+    invariants above leave open."""
+    g = _golden("db4_taps.txt")
+    want = np.array(g["h_sqrt2"]) / math.sqrt(2.0)
+    # the table prints 16 decimals (+-5e-17); FP64 spacing near 0.5 is 1.1e-16
+    assert np.max(np.abs(db.filter_taps(4) - want)) < 3e-16
+
+
+def _zeros_off_minus_one(h, p):
+    """Zeros of the polynomial sum_k h_k z^(k+p-1) other than the p-fold
+    zero at z = -1, found by dividing ((1+z)/2)^p out of the coefficients."""
+    lead_first = np.asarray(h, dtype=float)[::-1]
+    q, r = np.polydiv(lead_first, np.poly1d([0.5, 0.5]) ** p)
+    assert np.max(np.abs(r)) < 1e-13          # the p-fold zero at z = -1 is there
+    return np.roots(q)
+
+
+@pytest.mark.parametrize("p", [2, 3, 4, 5, 6, 7, 8])
+def test_filter_zero_locations(p):
+    """Extremal phase: with z = exp(-2 pi i xi), every zero of m0 apart from
+    z = -1 lies strictly outside the unit circle (the factor of
+    |m0|^2 = cos^{2p}(pi xi) P(sin^2 pi xi) that keeps the outer roots).  A
+    filter of another phase family (least asymmetric, or any mix) has zeros on
+    both sides and fails here."""
+    z = _zeros_off_minus_one(db.filter_taps(p), p)
+    assert len(z) == p - 1
+    assert np.min(np.abs(z)) > 1.5
+
+
+def _reflected_pair_taps(p):
+    """Another real orthonormal filter with the same |m0|: the oracle's taps
+    with one complex-conjugate pair of zeros z, conj(z) moved to 1/conj(z), 1/z
+    (a planted phase mistake, used only to show the pins reject it)."""
+    h = db.filter_taps(p)
+    z = _zeros_off_minus_one(h, p)
+    k = int(np.argmax(np.abs(z.imag)))
+    assert abs(z[k].imag) > 1e-3
+    pair = [z[k], np.conj(z[k])]
+    rest = [w for i, w in enumerate(z) if not (np.isclose(w, pair[0]) or np.isclose(w, pair[1]))]
+    new = rest + [1 / np.conj(pair[0]), 1 / np.conj(pair[1])]
+    poly = np.poly1d([0.5, 0.5]) ** p * np.poly1d(np.poly(new))
+    c = np.real(poly.coeffs[::-1])
+    return c / c.sum()
+
+
+@pytest.mark.parametrize("p", [3, 4, 6])
+def test_phase_pins_reject_other_factorizations(p):
+    """The planted filter passes every invariant of test_filter_invariants
+    (sum, vanishing moments, double-shift orthonormality) but fails the zero
+    location pin and, for p = 4, the published table."""
+    alt = _reflected_pair_taps(p)
+    k = db.tap_indices(p).astype(float)
+    assert abs(alt.sum() - 1) < 1e-13
+    for j in range(p):
+        assert abs(np.sum((-1) ** k * (k / p) ** j * alt)) < 1e-12
+    for l in range(1, p):
+        assert abs(np.dot(alt[:-2 * l], alt[2 * l:])) < 1e-12
+    assert abs(np.dot(alt, alt) - 0.5) < 1e-12
+    assert np.max(np.abs(alt - db.filter_taps(p))) > 1e-3
+    assert np.min(np.abs(_zeros_off_minus_one(alt, p))) < 1.0
+    if p == 4:
+        want = np.array(_golden("db4_taps.txt")["h_sqrt2"]) / math.sqrt(2.0)
+        assert np.max(np.abs(alt - want)) > 1e-3
+
+
 # ---------------------------------------------------------------- phi-hat (O2)
 
 def test_haar_product_matches_closed_form():
