@@ -93,6 +93,36 @@ def column_1d(xi, J: int, p: int, n: int) -> np.ndarray:
     return scale * half_turn_phase(xi, -1.0) * cdv.right_phi_hat(eta, p)[N - 1 - n]
 
 
+def columns_subset_1d(xi, J: int, p: int, ns) -> dict:
+    """{n: b_n(xi)} for the listed columns n, by the formulas of columns_1d
+    (Sec. 4), with phi-hat and the boundary transforms evaluated once for all
+    requested columns rather than once per column."""
+    check_scale(J, p)
+    xi = np.asarray(xi, dtype=np.float64)
+    N = 1 << J
+    eta = xi / N
+    scale = 2.0 ** (-J / 2.0)
+    nb = n_boundary(p)
+    ns = sorted(set(int(n) for n in ns))
+    if any(not 0 <= n < N for n in ns):
+        raise ValueError("column index out of range")
+    out = {}
+    inner = [n for n in ns if nb <= n < N - nb]
+    if inner:
+        ph = db.phi_hat(eta, p)
+        for n in inner:
+            out[n] = scale * unit_phase([n - N // 2], eta, -1.0)[0] * ph
+    if any(n < nb for n in ns):
+        L = cdv.left_phi_hat(eta, p)
+        for n in (n for n in ns if n < nb):
+            out[n] = scale * half_turn_phase(xi, +1.0) * L[n]
+    if any(n >= N - nb for n in ns):
+        R = cdv.right_phi_hat(eta, p)
+        for n in (n for n in ns if n >= N - nb):
+            out[n] = scale * half_turn_phase(xi, -1.0) * R[N - 1 - n]
+    return out
+
+
 def dense_T_1d(xi, J: int, p: int) -> np.ndarray:
     """T of shape (M, N), 1D."""
     return columns_1d(xi, J, p).T.copy()

@@ -50,7 +50,7 @@ void dfree(P*& ptr) {
 template <class T>
 void free_prec(gs::PrecData<T>& d) {
     dfree(d.pos); dfree(d.chx); dfree(d.chy); dfree(d.smu); dfree(d.win); dfree(d.deap); dfree(d.tw);
-    dfree(d.grid); dfree(d.sr); dfree(d.sc); dfree(d.part); dfree(d.vbuf); dfree(d.ybuf); dfree(d.xbuf);
+    dfree(d.grid); dfree(d.sr); dfree(d.sc); dfree(d.part); dfree(d.vbuf); dfree(d.ybuf);
     d.present = false;
 }
 
@@ -59,7 +59,7 @@ void free_plan(gs::Plan& P) {
     free_prec(P.d32);
     dfree(P.perm); dfree(P.cell_start); dfree(P.tile_order);
     dfree(P.smu64); dfree(P.b); dfree(P.r); dfree(P.q); dfree(P.ps); dfree(P.ss);
-    dfree(P.q32); dfree(P.r32); dfree(P.p32); dfree(P.s32);
+    dfree(P.q32); dfree(P.r32); dfree(P.p32); dfree(P.s32); dfree(P.xbest);
     dfree(P.red); dfree(P.scal); dfree(P.hist);
     if (P.host_scal) (void)hipHostFree(P.host_scal);
     P.host_scal = nullptr;
@@ -159,8 +159,6 @@ hipError_t upload_prec(gs::Plan& P, const HostPoints& H, const std::vector<doubl
     GS_HIP_TRY(dalloc(P, d.part, d.part_elems));
     GS_HIP_TRY(dalloc(P, d.vbuf, M));
     GS_HIP_TRY(dalloc(P, d.ybuf, M));
-    const size_t ncoef = P.dim == 2 ? (size_t)P.N * P.N : (size_t)P.N;
-    GS_HIP_TRY(dalloc(P, d.xbuf, ncoef));
     (void)s;
     return hipSuccess;
 }
@@ -243,7 +241,7 @@ int gs_plan(gs_plan_t** out, int dim, int J, int p, int64_t M, const double* xi,
     if (p < 1 || p > 8) return GS_ERR_UNSUPPORTED;
     if (J < 1 || J > (dim == 2 ? 11 : 20)) return GS_ERR_UNSUPPORTED;
     if ((1 << J) < 2 * p) return GS_ERR_UNSUPPORTED;
-    // FP32 positions: 32-bit fixed point, J + 1 bits of cell, >= 17 bits of offset
+    // FP32 positions: 32-bit fixed point, log2(grid) bits of cell, >= 17 bits of offset
     if (precision != GS_F64 && J > 14) return GS_ERR_UNSUPPORTED;
     for (int64_t i = 0; i < M * dim; ++i)
         if (!std::isfinite(xi[i])) return GS_ERR_BAD_NODES;
@@ -259,7 +257,10 @@ int gs_plan(gs_plan_t** out, int dim, int J, int p, int64_t M, const double* xi,
     }
     gs::Plan& P = h->impl;
     P.dim = dim; P.J = J; P.p = p; P.nb = (p == 1) ? 0 : p; P.N = 1 << J; P.M = M; P.precision = precision;
-    P.ng = 2 * P.N; P.G = J + 1;
+    // oversampling 2, except that the grid is never narrower than 16 cells:
+    // every window (at most 14 taps) then covers distinct cells, so each grid
+    // value enters a sum once (a wrapped window would sum it several times)
+    P.ng = std::max(2 * P.N, gs::MIN_GRID); P.G = gs::ilog2(P.ng);
     if (dim == 1 && P.ng > gs::FFT_MAX_LDS) {
         P.lg1 = P.G / 2; P.lg2 = P.G - P.lg1;
     } else {

@@ -172,15 +172,20 @@ __global__ void __launch_bounds__(RT) update_xr_kernel(double* __restrict__ scal
     }
 }
 
-// p = s + beta p, beta = ||s||^2 / gamma (gamma not yet updated)
+// p = s + beta p, beta = ||s||^2 / gamma (gamma not yet updated).  With
+// xbest (reduced-precision recurrences), x is also copied there whenever its
+// normal residual ||s||^2 is the smallest of the run, so that a recurrence
+// stopped past its accuracy floor can return its best iterate.
 template <class T, class Tp>
 __global__ void __launch_bounds__(RT) update_p_kernel(const double* __restrict__ scal, const double* __restrict__ red,
                                                       cx<double>* __restrict__ p, const cx<T>* __restrict__ s,
-                                                      cx<Tp>* __restrict__ pT, int64_t nx) {
+                                                      cx<Tp>* __restrict__ pT, int64_t nx,
+                                                      const cx<double>* __restrict__ x, cx<double>* __restrict__ xbest) {
     __shared__ double sh[RT];
     const double gnew = sum_partials(red, sh);
     if (scal[S_DONE] != 0.0 || scal[S_BREAK] != 0.0) return;
     const double beta = gnew / scal[S_GAMMA];
+    const bool keep = xbest && gnew < scal[S_GMIN];
     for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < nx; i += (int64_t)gridDim.x * RT) {
         const cx<double> sv = to64(s[i]);
         cx<double> pv = p[i];
@@ -188,7 +193,13 @@ __global__ void __launch_bounds__(RT) update_p_kernel(const double* __restrict__
         pv.y = sv.y + beta * pv.y;
         p[i] = pv;
         if (pT) pT[i] = mk<Tp>((Tp)pv.x, (Tp)pv.y);
+        if (keep) xbest[i] = x[i];
     }
+}
+
+__global__ void copy_kernel(const cx<double>* __restrict__ a, cx<double>* __restrict__ o, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = a[i];
 }
 
 // gamma = ||s||^2 ; iteration count, history, convergence test
@@ -241,6 +252,7 @@ hipError_t solver_alloc(Plan& P) {
     GS_HIP_TRY(alloc(P.ps, nx));
     GS_HIP_TRY(alloc(P.ss, nx));
     if (P.d32.present) {
+        GS_HIP_TRY(alloc(P.xbest, nx));
         GS_HIP_TRY(alloc(P.q32, M));
         GS_HIP_TRY(alloc(P.r32, M));
         GS_HIP_TRY(alloc(P.p32, nx));
@@ -272,6 +284,7 @@ struct Ops<double> {
     cx<double>* pa() const { return P.ps; }
     cx<double>* rcopy() const { return nullptr; }
     cx<double>* pcopy() const { return nullptr; }
+    cx<double>* xbest() const { return nullptr; }   // FP64 recurrences do not stall
 };
 template <>
 struct Ops<float> {
@@ -282,6 +295,7 @@ struct Ops<float> {
     cx<float>* pa() const { return P.p32; }
     cx<float>* rcopy() const { return P.r32; }
     cx<float>* pcopy() const { return P.p32; }
+    cx<double>* xbest() const { return P.xbest; }
 };
 
 constexpr int AFLAGS = GS_WEIGHTED | GS_SORTED;
@@ -289,9 +303,10 @@ constexpr int AFLAGS = GS_WEIGHTED | GS_SORTED;
 // Starts CGLS from x (already on device, FP64) given r = b - A x in P.r (and
 // its apply-precision copy).  Computes s = A^H r, gamma, p = s.
 template <class T>
-hipError_t cgls_start(const Plan& P, hipStream_t st, int set_ref, double* hist, int hist_len) {
+hipError_t cgls_start(const Plan& P, const cx<double>* x, hipStream_t st, int set_ref, double* hist, int hist_len) {
     Ops<T> o{P};
     const int64_t nx = P.dim == 2 ? (int64_t)P.N * P.N : P.N;
+    if (o.xbest()) hipLaunchKernelGGL(copy_kernel, dim3(nb256(nx)), dim3(256), 0, st, x, o.xbest(), nx);
     GS_HIP_TRY(launch_apply_TH<T>(P, o.ra(), o.sa(), AFLAGS, st));
     hipLaunchKernelGGL((norm2_partial_kernel<T>), dim3(RB), dim3(RT), 0, st, o.sa(), nx, P.red);
     hipLaunchKernelGGL((init_p_kernel<T, T>), dim3(nb256(nx)), dim3(256), 0, st, o.sa(), P.ps, o.pcopy(), nx);
@@ -312,7 +327,7 @@ hipError_t cgls_iteration(const Plan& P, cx<double>* x, hipStream_t st, double* 
     GS_HIP_TRY(launch_apply_TH<T>(P, o.ra(), o.sa(), AFLAGS, st));
     hipLaunchKernelGGL((norm2_partial_kernel<T>), dim3(RB), dim3(RT), 0, st, o.sa(), nx, P.red);
     hipLaunchKernelGGL((update_p_kernel<T, T>), dim3(256), dim3(RT), 0, st, P.scal, P.red, P.ps, o.sa(), o.pcopy(),
-                       nx);
+                       nx, (const cx<double>*)x, o.xbest());
     hipLaunchKernelGGL(step_scalars_kernel, dim3(1), dim3(RT), 0, st, P.scal, P.red, hist, hist_len);
     return hipGetLastError();
 }
@@ -388,7 +403,7 @@ int solve_setup(const Plan& P, const cx<double>* y, cx<double>* x, const gs_solv
     } else {
         hipLaunchKernelGGL((zero_kernel<double>), dim3(nb256(nx)), dim3(256), 0, st, x, nx);
     }
-    if (!hipok(cgls_start<T>(P, st, 0, hist, hist_len))) return GS_ERR_HIP;
+    if (!hipok(cgls_start<T>(P, x, st, 0, hist, hist_len))) return GS_ERR_HIP;
     if (warm && opt.warm_start == 2) {
         // guarded start: keep x0 only if ||A^H(b - A x0)|| < ||A^H b|| (zero start's value)
         if (!hipok(hipMemcpyAsync(P.host_scal, P.scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, st)) ||
@@ -400,7 +415,7 @@ int solve_setup(const Plan& P, const cx<double>* y, cx<double>* x, const gs_solv
             hipLaunchKernelGGL((zero_kernel<double>), dim3(nb256(nx)), dim3(256), 0, st, x, nx);
             hipLaunchKernelGGL((init_b_kernel<T>), dim3(nb256(M)), dim3(256), 0, st, y, P.perm, P.smu64, M, P.b,
                                P.r, o.rcopy());
-            if (!hipok(cgls_start<T>(P, st, 0, hist, hist_len))) return GS_ERR_HIP;
+            if (!hipok(cgls_start<T>(P, x, st, 0, hist, hist_len))) return GS_ERR_HIP;
         }
     }
     if (warm_used) *warm_used = warm ? 1 : 0;
@@ -420,6 +435,16 @@ int solve_finish(const Plan& P, cx<double>* x, const gs_solve_opts& opt, gs_solv
     double rel = P.host_scal[S_REF] > 0 ? std::sqrt(P.host_scal[S_GAMMA]) / P.host_scal[S_REF] : 0.0;
     double rel64 = -1;
     const bool refine = opt.refine_fp64 && std::is_same<T, float>::value && P.d64.present;
+    // A stall (the reduced-precision recurrence passed its accuracy floor) ends
+    // the run without a breakdown: x goes back to the run's best iterate and
+    // the status follows the residual.
+    auto settle_stall = [&]() {
+        if (P.host_scal[S_STALL] == 0.0 || !o.xbest()) return;
+        hipLaunchKernelGGL(copy_kernel, dim3(nb256(nx)), dim3(256), 0, st, (const cx<double>*)o.xbest(), x, nx);
+        broke = false;
+        rel = P.host_scal[S_REF] > 0 ? std::sqrt(P.host_scal[S_GMIN]) / P.host_scal[S_REF] : 0.0;
+    };
+    settle_stall();
     // mixed form: a stop of the FP32 recurrence (stall or breakdown) is not
     // final; the FP64 residual decides, and restarts resume from x
     if (refine) {
@@ -445,12 +470,13 @@ int solve_finish(const Plan& P, cx<double>* x, const gs_solve_opts& opt, gs_solv
             ++restarts;
             // restart the FP32 recurrence from x with the FP64 residual
             hipLaunchKernelGGL((convert_kernel<T>), dim3(nb256(M)), dim3(256), 0, st, P.r, o.ra(), M);
-            if (!hipok(cgls_start<T>(P, st, 0, nullptr, 0))) return GS_ERR_HIP;
+            if (!hipok(cgls_start<T>(P, x, st, 0, nullptr, 0))) return GS_ERR_HIP;
             if (!hipok(cgls_run<T>(P, x, st, opt.max_iter - used, std::max(1, opt.check_every), nullptr, 0, done,
                                    broke)))
                 return GS_ERR_HIP;
             used += (int)P.host_scal[S_ITER];
             rel = P.host_scal[S_REF] > 0 ? std::sqrt(P.host_scal[S_GAMMA]) / P.host_scal[S_REF] : 0.0;
+            settle_stall();
         }
         done = rel64 <= opt.rel_tol;
         broke = !std::isfinite(rel64);
@@ -709,11 +735,10 @@ extern "C" int gs_solve_batch(const gs_plan_t* const* plans, int count, const vo
         int r = it.fp32 ? solve_finish<float>(*it.P, it.x, *opts, infos[i], user, it.done, it.broke)
                         : solve_finish<double>(*it.P, it.x, *opts, infos[i], user, it.done, it.broke);
         infos[i].warm_start_used = it.warm_used;
-        if (r < 0) {
-            cleanup();
-            return r;
-        }
-        if (r == GS_NOT_CONVERGED && worst == GS_OK) worst = r;
+        // every problem is finished and reported; the call returns the worst
+        // status (an error before GS_NOT_CONVERGED before GS_OK)
+        if (r < 0 && worst >= 0) worst = r;
+        else if (r == GS_NOT_CONVERGED && worst == GS_OK) worst = r;
     }
     cleanup();
     return worst;

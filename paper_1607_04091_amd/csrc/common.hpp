@@ -65,11 +65,11 @@ struct PrecData {
     C* part = nullptr;     // partial sums
     C* vbuf = nullptr;     // [M] adjoint input in internal order (weighted)
     C* ybuf = nullptr;     // [M] apply output in internal order (solver)
-    C* xbuf = nullptr;     // [N^dim] coefficient staging (solver)
     size_t part_elems = 0;
 };
 
 constexpr int FFT_MAX_LDS = 4096;   // largest single-pass FFT held in LDS
+constexpr int MIN_GRID = 16;        // smallest NFFT grid side: at least the widest window
 constexpr int TILE = 32;            // 2D point tiles: TILE x TILE grid cells
 
 // sort key of a 2D cell: tile-major (tiles of ts x ts cells), row-major inside a tile
@@ -97,6 +97,7 @@ struct Plan {
     cx<double> *ps = nullptr, *ss = nullptr;                  // [N^dim]
     cx<float> *q32 = nullptr, *r32 = nullptr;                 // [M]   FP32-apply operands
     cx<float> *p32 = nullptr, *s32 = nullptr;                 // [N^dim]
+    cx<double>* xbest = nullptr;    // [N^dim] best iterate of a reduced-precision recurrence
     double* red = nullptr;          // reduction partials [red_blocks]
     double* scal = nullptr;         // device scalars
     double* hist = nullptr;         // residual history (device)
@@ -118,9 +119,27 @@ template <class T> const PrecData<T>& prec(const Plan& p);
 template <> inline const PrecData<double>& prec<double>(const Plan& p) { return p.d64; }
 template <> inline const PrecData<float>& prec<float>(const Plan& p) { return p.d32; }
 
+// Transform workspace of one adjoint apply: the oversampled grid, the 2D side
+// grids, the partial sums and the adjoint input in sorted order.  By default
+// the plan's own buffers; the allocation-free entry point passes a carve-up of
+// its static device array instead.
+template <class T> struct Work {
+    cx<T>* grid = nullptr;
+    cx<T>* sr = nullptr;
+    cx<T>* sc = nullptr;
+    cx<T>* part = nullptr;
+    cx<T>* vbuf = nullptr;
+};
+template <class T> inline Work<T> plan_work(const PrecData<T>& d) {
+    Work<T> w;
+    w.grid = d.grid; w.sr = d.sr; w.sc = d.sc; w.part = d.part; w.vbuf = d.vbuf;
+    return w;
+}
+
 // launch helpers (defined in nfft.hip / fft.hip)
 template <class T> hipError_t launch_apply_T(const Plan& P, const C_t<T>* x, C_t<T>* y, int flags, hipStream_t s);
-template <class T> hipError_t launch_apply_TH(const Plan& P, const C_t<T>* u, C_t<T>* x, int flags, hipStream_t s);
+template <class T> hipError_t launch_apply_TH(const Plan& P, const C_t<T>* u, C_t<T>* x, int flags, hipStream_t s,
+                                              const Work<T>* work = nullptr);
 
 // column split of a 2D grid of side ng for the register column transform
 // (0: single-pass LDS transform, natural row order)
@@ -139,3 +158,4 @@ struct gs_plan {
         hipError_t _e = (expr);                   \
         if (_e != hipSuccess) return _e;          \
     } while (0)
+static_assert(gs::MIN_GRID >= gs::W64 && gs::MIN_GRID >= gs::W32, "a window must fit the smallest grid");

@@ -20,7 +20,8 @@
 namespace gs {
 
 template <class T> hipError_t interp2d_tile(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hipStream_t s);
-template <class T> hipError_t adjoint2d_tile(const Plan& P, const cx<T>* u, cx<T>* x, int flags, hipStream_t s);
+template <class T> hipError_t adjoint2d_tile(const Plan& P, const cx<T>* u, cx<T>* x, int flags, hipStream_t s,
+                                             const Work<T>& wk);
 size_t adjoint2d_part_elems(int ng, int ts, int nb, int w);
 
 // ------------------------------------------------------------------ helpers
@@ -591,33 +592,34 @@ hipError_t launch_apply_T(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hi
 }
 
 template <class T>
-hipError_t launch_apply_TH(const Plan& P, const cx<T>* u, cx<T>* x, int flags, hipStream_t s) {
+hipError_t launch_apply_TH(const Plan& P, const cx<T>* u, cx<T>* x, int flags, hipStream_t s, const Work<T>* work) {
     const PrecData<T>& d = prec<T>(P);
+    const Work<T> wk = work ? *work : plan_work(d);
     const Geo<T> g = make_geo<T>(P);
     constexpr int W = WinParams<T>::W, DEG = WinParams<T>::DEG;
     const int N = P.N, nb = P.nb, ng = P.ng;
     if (P.dim == 2 && P.ts == TILE) {
-        GS_HIP_TRY(adjoint2d_tile<T>(P, u, x, flags, s));
+        GS_HIP_TRY(adjoint2d_tile<T>(P, u, x, flags, s, wk));
         if (P.cr1) {
-            auto mk = [&](int L) { return GridLoad<T>{d.grid, L, N, nb, 0}; };
-            GS_TIMED(K_FFT_COLS_TH, GS_HIP_TRY((launch_colfft_split<T, +1>(P.cr1, ng, mk, d.grid, d.tw, N, nb, 1, s))));
+            auto mk = [&](int L) { return GridLoad<T>{wk.grid, L, N, nb, 0}; };
+            GS_TIMED(K_FFT_COLS_TH, GS_HIP_TRY((launch_colfft_split<T, +1>(P.cr1, ng, mk, wk.grid, d.tw, N, nb, 1, s))));
         } else {
-            GS_TIMED(K_FFT_COLS_TH, GS_HIP_TRY((launch_fft<T, +1>(OpCols<T>{d.grid, N, nb, ng, 0}, ng, ng,
+            GS_TIMED(K_FFT_COLS_TH, GS_HIP_TRY((launch_fft<T, +1>(OpCols<T>{wk.grid, N, nb, ng, 0}, ng, ng,
                                                                 col_batch<T>(ng), d.tw, ng, s))));
         }
-        const OpTH2Rows<T> rows{d.grid, d.sr, x, d.deap, N, nb, ng, P.cr1, P.cr2};
+        const OpTH2Rows<T> rows{wk.grid, wk.sr, x, d.deap, N, nb, ng, P.cr1, P.cr2};
         if (nb) {
             using J = OpJoin<T, OpTH2Rows<T>, OpTH2SideCols<T>>;
-            GS_TIMED(K_FFT_ROWS_TH, GS_HIP_TRY((launch_fft<T, +1>(J{rows, OpTH2SideCols<T>{d.sc, x, d.deap, N, nb, ng}, N},
+            GS_TIMED(K_FFT_ROWS_TH, GS_HIP_TRY((launch_fft<T, +1>(J{rows, OpTH2SideCols<T>{wk.sc, x, d.deap, N, nb, ng}, N},
                                                                 N + 2 * nb, ng, 1, d.tw, ng, s))));
         } else {
             GS_TIMED(K_FFT_ROWS_TH, GS_HIP_TRY((launch_fft<T, +1>(rows, N, ng, 1, d.tw, ng, s))));
         }
         return hipSuccess;
     }
-    cx<T>* v = d.vbuf;
-    cx<T>* vI = d.part;  // first M entries of the partial buffer
-    cx<T>* part = d.part + P.M;
+    cx<T>* v = wk.vbuf;
+    cx<T>* vI = wk.part;  // first M entries of the partial buffer
+    cx<T>* part = wk.part + P.M;
     GS_TIMED(K_ADJ_PREP, hipLaunchKernelGGL((adj_prep_kernel<T>), dim3(nblk(P.M, 256)), dim3(256), 0, s, g, u, v, vI,
                                             flags));
     GS_HIP_TRY(hipGetLastError());
@@ -633,7 +635,7 @@ hipError_t launch_apply_TH(const Plan& P, const cx<T>* u, cx<T>* x, int flags, h
     }
     if (P.dim == 2) {
         GS_TIMED(K_SPREAD2D, hipLaunchKernelGGL((spread2d_kernel<T, W, DEG>), dim3(nblk((int64_t)ng * ng, 256)),
-                                                dim3(256), 0, s, g, vI, d.grid));
+                                                dim3(256), 0, s, g, vI, wk.grid));
         GS_HIP_TRY(hipGetLastError());
         if (nb) {
             const int strip = std::min(ng, 64);
@@ -644,35 +646,35 @@ hipError_t launch_apply_TH(const Plan& P, const cx<T>* u, cx<T>* x, int flags, h
                                                      part, strip));
             GS_HIP_TRY(hipGetLastError());
             GS_TIMED(K_REDUCE_STRIPS, hipLaunchKernelGGL((reduce_strips_kernel<T>), dim3(nblk(count, 256)), dim3(256),
-                                                         0, s, part, d.sr, nstrip, count));
+                                                         0, s, part, wk.sr, nstrip, count));
             GS_HIP_TRY(hipGetLastError());
             GS_TIMED(K_SIDE_COLS, hipLaunchKernelGGL((side_cols_partial_kernel<T, W, DEG>),
                                                      dim3(nblk((int64_t)nstrip * count, 256)), dim3(256), 0, s, g, v,
                                                      part, strip));
             GS_HIP_TRY(hipGetLastError());
             GS_TIMED(K_REDUCE_STRIPS, hipLaunchKernelGGL((reduce_strips_kernel<T>), dim3(nblk(count, 256)), dim3(256),
-                                                         0, s, part, d.sc, nstrip, count));
+                                                         0, s, part, wk.sc, nstrip, count));
             GS_HIP_TRY(hipGetLastError());
         }
-        GS_TIMED(K_FFT_COLS_TH, GS_HIP_TRY((launch_fft<T, +1>(OpCols<T>{d.grid, N, nb, ng, 0}, ng, ng,
+        GS_TIMED(K_FFT_COLS_TH, GS_HIP_TRY((launch_fft<T, +1>(OpCols<T>{wk.grid, N, nb, ng, 0}, ng, ng,
                                                             col_batch<T>(ng), d.tw, ng, s))));
-        GS_TIMED(K_FFT_ROWS_TH, GS_HIP_TRY((launch_fft<T, +1>(OpTH2Rows<T>{d.grid, d.sr, x, d.deap, N, nb, ng}, N, ng,
+        GS_TIMED(K_FFT_ROWS_TH, GS_HIP_TRY((launch_fft<T, +1>(OpTH2Rows<T>{wk.grid, wk.sr, x, d.deap, N, nb, ng}, N, ng,
                                                             1, d.tw, ng, s))));
         if (nb)
             GS_TIMED(K_FFT_SIDECOLS_TH,
-                     GS_HIP_TRY((launch_fft<T, +1>(OpTH2SideCols<T>{d.sc, x, d.deap, N, nb, ng}, 2 * nb, ng,
+                     GS_HIP_TRY((launch_fft<T, +1>(OpTH2SideCols<T>{wk.sc, x, d.deap, N, nb, ng}, 2 * nb, ng,
                                                    1, d.tw, ng, s))));
     } else {
         GS_TIMED(K_SPREAD1D, hipLaunchKernelGGL((spread1d_kernel<T, W, DEG>), dim3(nblk(ng, 256)), dim3(256), 0, s, g,
-                                                vI, d.grid));
+                                                vI, wk.grid));
         GS_HIP_TRY(hipGetLastError());
         const Crop1<T> crop{x, d.deap, N, nb, ng};
         if (ng <= FFT_MAX_LDS) {
-            GS_TIMED(K_FFT1_TH, GS_HIP_TRY((launch_fft<T, +1>(OpTH1Single<T>{d.grid, crop}, 1, ng, 1, d.tw, ng, s))));
+            GS_TIMED(K_FFT1_TH, GS_HIP_TRY((launch_fft<T, +1>(OpTH1Single<T>{wk.grid, crop}, 1, ng, 1, d.tw, ng, s))));
         } else {
-            GS_TIMED(K_FFT1_TH, GS_HIP_TRY((launch_fft<T, +1>(OpTH1P1<T>{d.grid, d.tw, P.n2, ng}, P.n1, P.n2, 1, d.tw,
+            GS_TIMED(K_FFT1_TH, GS_HIP_TRY((launch_fft<T, +1>(OpTH1P1<T>{wk.grid, d.tw, P.n2, ng}, P.n1, P.n2, 1, d.tw,
                                                             ng, s))));
-            GS_TIMED(K_FFT1_TH, GS_HIP_TRY((launch_fft<T, +1>(OpTH1P2<T>{d.grid, crop, P.n2}, P.n2, P.n1,
+            GS_TIMED(K_FFT1_TH, GS_HIP_TRY((launch_fft<T, +1>(OpTH1P2<T>{wk.grid, crop, P.n2}, P.n2, P.n1,
                                                             col_batch<T>(P.n1), d.tw, ng, s))));
         }
     }
@@ -681,8 +683,10 @@ hipError_t launch_apply_TH(const Plan& P, const cx<T>* u, cx<T>* x, int flags, h
 
 template hipError_t launch_apply_T<float>(const Plan&, const cx<float>*, cx<float>*, int, hipStream_t);
 template hipError_t launch_apply_T<double>(const Plan&, const cx<double>*, cx<double>*, int, hipStream_t);
-template hipError_t launch_apply_TH<float>(const Plan&, const cx<float>*, cx<float>*, int, hipStream_t);
-template hipError_t launch_apply_TH<double>(const Plan&, const cx<double>*, cx<double>*, int, hipStream_t);
+template hipError_t launch_apply_TH<float>(const Plan&, const cx<float>*, cx<float>*, int, hipStream_t,
+                                           const Work<float>*);
+template hipError_t launch_apply_TH<double>(const Plan&, const cx<double>*, cx<double>*, int, hipStream_t,
+                                            const Work<double>*);
 
 // partial-buffer size needed by the adjoint (elements)
 size_t adjoint_part_elems(int dim, int64_t M, int nb, int ng) {

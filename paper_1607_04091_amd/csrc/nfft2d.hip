@@ -3,26 +3,25 @@
 // Points are sorted tile-major (tiles of TS x TS grid cells, row-major cells
 // inside a tile), so the points of a tile are contiguous.
 //
-// Forward (interp_tile_kernel): one workgroup per tile stages the grid
-// window it needs (TS+W-1 squared), the matching segments of the 1D side
-// grids and the corner block of X in LDS; each thread then evaluates one
-// point: interior 2D interpolation, the four side blocks (1D interpolation
-// of the boundary rows/columns), the four corner blocks, the scales
-// D_x D_y, boundary channels and sqrt(mu).
+// Forward: interp_bnd_kernel evaluates the boundary part of each point (the
+// four side blocks by 1D interpolation of the side grids, the four corner
+// blocks densely) into a sorted-order buffer; interp_tile_kernel stages the
+// tile's grid window (TS+W-1 squared) in LDS, interpolates the interior,
+// adds the boundary part and applies D_x D_y and sqrt(mu).
 //
-// Adjoint (adjoint_tile_kernel): one workgroup per tile owns the points of
-// the tile.  Per chunk of points it stages, once per point, the window taps
-// and the channel products in LDS; then
-//   * column-owner threads (one per padded output column and block of cell
-//     rows) gather the interior 2D spread into register accumulators for the
-//     W+RB-1 output rows that block touches, plus the row-side (x-boundary)
-//     channels;
-//   * row-owner threads gather the column-side (y-boundary) channels;
-//   * one wavefront accumulates the corner blocks sum_m conj(ax_r ay_c) v_m
-//     as a matrix product with MFMA.
-// The tile writes its partial padded grid, side and corner sums; a merge
-// kernel adds the partials of neighbouring tiles in a fixed order.  No
-// atomics are used, and results are bitwise reproducible.
+// Adjoint: adj_gather_kernel brings the (weighted) input into sorted order.
+// Two tile kernels then read the tile's points in chunks staged in LDS
+// (window taps and channel products, computed once per point):
+//   * adj_interior_kernel: column-owner threads (one per padded output column
+//     and block of cell rows) gather the interior 2D spread into register
+//     accumulators, plus the row-side (x-boundary) channels;
+//   * adj_boundary_kernel: four wavefronts sum the column-side (y-boundary)
+//     channels per cell row and split the corner products
+//     sum_m conj(ax_r ay_c) v_m among themselves as 16x16x4 MFMA steps.
+// Each tile writes its partial padded grid, side and corner sums;
+// merge_grid_kernel and merge_sides_kernel add the partials of neighbouring
+// tiles in a fixed order.  No atomics are used, and results are bitwise
+// reproducible.
 #include <algorithm>
 
 #include "common.hpp"
@@ -851,8 +850,7 @@ hipError_t interp2d_tile_nb(const Plan& P, const cx<T>* x, cx<T>* y, int flags, 
 }
 
 template <class T, int NB>
-hipError_t adjoint2d_tile_nb(const Plan& P, const cx<T>* u, cx<T>* x, int flags, hipStream_t s) {
-    const PrecData<T>& d = prec<T>(P);
+hipError_t adjoint2d_tile_nb(const Plan& P, const cx<T>* u, cx<T>* x, int flags, hipStream_t s, const Work<T>& d) {
     const TileGeo<T> g = make_tile_geo<T>(P);
     constexpr int W = TileWin<T>::W, DEG = TileWin<T>::DEG;
     constexpr int PW = TILE_TS + W - 1;
@@ -933,24 +931,26 @@ hipError_t interp2d_tile(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hip
 }
 
 template <class T>
-hipError_t adjoint2d_tile(const Plan& P, const cx<T>* u, cx<T>* x, int flags, hipStream_t s) {
+hipError_t adjoint2d_tile(const Plan& P, const cx<T>* u, cx<T>* x, int flags, hipStream_t s, const Work<T>& wk) {
     switch (P.nb) {
-        case 0: return adjoint2d_tile_nb<T, 0>(P, u, x, flags, s);
-        case 2: return adjoint2d_tile_nb<T, 2>(P, u, x, flags, s);
-        case 3: return adjoint2d_tile_nb<T, 3>(P, u, x, flags, s);
-        case 4: return adjoint2d_tile_nb<T, 4>(P, u, x, flags, s);
-        case 5: return adjoint2d_tile_nb<T, 5>(P, u, x, flags, s);
-        case 6: return adjoint2d_tile_nb<T, 6>(P, u, x, flags, s);
-        case 7: return adjoint2d_tile_nb<T, 7>(P, u, x, flags, s);
-        case 8: return adjoint2d_tile_nb<T, 8>(P, u, x, flags, s);
+        case 0: return adjoint2d_tile_nb<T, 0>(P, u, x, flags, s, wk);
+        case 2: return adjoint2d_tile_nb<T, 2>(P, u, x, flags, s, wk);
+        case 3: return adjoint2d_tile_nb<T, 3>(P, u, x, flags, s, wk);
+        case 4: return adjoint2d_tile_nb<T, 4>(P, u, x, flags, s, wk);
+        case 5: return adjoint2d_tile_nb<T, 5>(P, u, x, flags, s, wk);
+        case 6: return adjoint2d_tile_nb<T, 6>(P, u, x, flags, s, wk);
+        case 7: return adjoint2d_tile_nb<T, 7>(P, u, x, flags, s, wk);
+        case 8: return adjoint2d_tile_nb<T, 8>(P, u, x, flags, s, wk);
     }
     return hipErrorInvalidValue;
 }
 
 template hipError_t interp2d_tile<float>(const Plan&, const cx<float>*, cx<float>*, int, hipStream_t);
 template hipError_t interp2d_tile<double>(const Plan&, const cx<double>*, cx<double>*, int, hipStream_t);
-template hipError_t adjoint2d_tile<float>(const Plan&, const cx<float>*, cx<float>*, int, hipStream_t);
-template hipError_t adjoint2d_tile<double>(const Plan&, const cx<double>*, cx<double>*, int, hipStream_t);
+template hipError_t adjoint2d_tile<float>(const Plan&, const cx<float>*, cx<float>*, int, hipStream_t,
+                                          const Work<float>&);
+template hipError_t adjoint2d_tile<double>(const Plan&, const cx<double>*, cx<double>*, int, hipStream_t,
+                                           const Work<double>&);
 
 // partial-buffer elements needed by the 2D adjoint
 size_t adjoint2d_part_elems(int ng, int ts, int nb, int w) {

@@ -145,6 +145,30 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _is_device_tensor(t) -> bool:
+    return bool(getattr(t, "is_cuda", False))
+
+
+def _check_vec(t, dtype, numel, name, like=None):
+    """Validates a device vector handed to the library (input or output):
+    element type, element count, contiguity, and that it lives on a GPU (the
+    same one as `like`, if given).  Raises ValueError before any library call,
+    so a wrong buffer never reaches a kernel."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if not _is_device_tensor(t):
+        raise ValueError(f"{name} must be a GPU tensor")
+    if like is not None and t.device != like.device:
+        raise ValueError(f"{name} must be on {like.device}, got {t.device}")
+
+
 # ------------------------------------------------------------------ per-kernel timing
 
 def gs_profile_enable(enable: bool = True):
@@ -255,10 +279,10 @@ class Plan:
     def apply_T(self, x, y=None, weighted=False, sorted_order=False, f64=False, stream=None):
         import torch
         dt = self._dtype(f64)
-        if x.dtype != dt or not x.is_contiguous() or x.numel() != self.N ** self.dim:
-            raise ValueError(f"x must be a contiguous {dt} tensor with {self.N ** self.dim} elements")
+        _check_vec(x, dt, self.N ** self.dim, "x")
         if y is None:
             y = torch.empty(self.M, dtype=dt, device=x.device)
+        _check_vec(y, dt, self.M, "y", like=x)
         flags = _wflags(weighted) | (GS_SORTED if sorted_order else 0) | (GS_APPLY_F64 if f64 else 0)
         rc = _lib.gs_apply_T(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), flags,
                              _stream(stream))
@@ -269,10 +293,10 @@ class Plan:
     def apply_TH(self, u, x=None, weighted=False, sorted_order=False, f64=False, stream=None):
         import torch
         dt = self._dtype(f64)
-        if u.dtype != dt or not u.is_contiguous() or u.numel() != self.M:
-            raise ValueError(f"u must be a contiguous {dt} tensor with {self.M} elements")
+        _check_vec(u, dt, self.M, "u")
         if x is None:
             x = torch.empty(self.coef_shape(), dtype=dt, device=u.device)
+        _check_vec(x, dt, self.N ** self.dim, "x", like=u)
         flags = _wflags(weighted) | (GS_SORTED if sorted_order else 0) | (GS_APPLY_F64 if f64 else 0)
         rc = _lib.gs_apply_TH(self.handle, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(x.data_ptr()), flags,
                               _stream(stream))
@@ -283,12 +307,12 @@ class Plan:
     def solve(self, y, x=None, rel_tol=1e-6, max_iter=500, warm_start=False, refine_fp64=True, max_restarts=2,
               check_every=1, history=False, stream=None):
         import torch
-        if y.dtype != torch.complex128 or not y.is_contiguous() or y.numel() != self.M:
-            raise ValueError("y must be a contiguous complex128 tensor of length M")
+        _check_vec(y, torch.complex128, self.M, "y")
         if x is None:
             if warm_start:
                 raise ValueError("warm_start needs x")
             x = torch.zeros(self.coef_shape(), dtype=torch.complex128, device=y.device)
+        _check_vec(x, torch.complex128, self.N ** self.dim, "x", like=y)
         hist = np.zeros(max_iter + 1) if history else None
         # warm_start: False (x0 = 0), True (x holds x0) or "guarded" (x0 kept only if it beats x0 = 0)
         ws = 2 if warm_start == "guarded" else int(bool(warm_start))
@@ -341,10 +365,13 @@ def gs_solve_batch(plans, ys, xs=None, rel_tol=1e-6, max_iter=500, refine_fp64=T
     if n < 1 or len(ys) != n:
         raise ValueError("need one y per plan")
     for p, y in zip(plans, ys):
-        if y.dtype != torch.complex128 or not y.is_contiguous() or y.numel() != p.M:
-            raise ValueError("each y must be a contiguous complex128 tensor of length M")
+        _check_vec(y, torch.complex128, p.M, "y[i]")
     if xs is None:
         xs = [torch.zeros(p.coef_shape(), dtype=torch.complex128, device=y.device) for p, y in zip(plans, ys)]
+    if len(xs) != n:
+        raise ValueError("need one x per plan")
+    for p, y, x in zip(plans, ys, xs):
+        _check_vec(x, torch.complex128, p.N ** p.dim, "x[i]", like=y)
     vp = ctypes.c_void_p
     hp = (vp * n)(*[p.handle for p in plans])
     yp = (vp * n)(*[y.data_ptr() for y in ys])
@@ -434,6 +461,10 @@ class Cnn:
             x = x.unsqueeze(0)
         if x.dim() != 3 or tuple(x.shape[1:]) != (self.height, self.width):
             raise ValueError(f"{name} must have shape (batch, {self.height}, {self.width})")
+        if not 1 <= x.shape[0] <= self.max_batch:
+            raise ValueError(f"{name} must hold 1..{self.max_batch} images")
+        if not _is_device_tensor(x):
+            raise ValueError(f"{name} must be a GPU tensor")
         return x
 
     def forward(self, x, out=None, train=False, out_dtype=None, stream=None):
@@ -444,6 +475,10 @@ class Cnn:
             out = torch.empty(x.shape, dtype=out_dtype or x.dtype, device=x.device)
         if out is not None:
             out = self._images(out, "out")
+            if out.shape[0] != x.shape[0]:
+                raise ValueError(f"out holds {out.shape[0]} images, x {x.shape[0]}")
+            if not _is_device_tensor(out) or out.device != x.device:
+                raise ValueError(f"out must be on {x.device}")
         flags = (GS_CNN_IN_F64 if x.dtype == torch.complex128 else 0) | (GS_CNN_TRAIN if train else 0)
         if out is not None and out.dtype == torch.complex128:
             flags |= GS_CNN_OUT_F64

@@ -9,7 +9,7 @@ torch = pytest.importorskip("torch")
 from oracle import basis
 from workloads import grid, jitter_1d, spiral_2d, jitter_2d, voronoi_weights_1d, voronoi_weights_2d
 
-from gpu_util import rel, crandn, to_dev, to_host, say
+from gpu_util import assert_close, rel, crandn, to_dev, to_host, say
 
 pytestmark = pytest.mark.gpu
 
@@ -72,15 +72,15 @@ def test_apply_1d(gs, J, p, M, kind, prec):
     plan = gs.gs_plan(1, J, p, xi, mu, precision=prec)
     dt = torch.complex128 if prec == 0 else torch.complex64
     y = to_host(plan.apply_T(to_dev(x, dt)))
-    assert rel(y, T @ x) < TOL[prec]
+    assert_close(y, T @ x, TOL[prec], "y")
     z = to_host(plan.apply_TH(to_dev(u, dt)))
-    assert rel(z, T.conj().T @ u) < TOL[prec]
+    assert_close(z, T.conj().T @ u, TOL[prec], "z")
     if mu is not None:
         s = np.sqrt(mu)
         yw = to_host(plan.apply_T(to_dev(x, dt), weighted=True))
-        assert rel(yw, s * (T @ x)) < TOL[prec]
+        assert_close(yw, s * (T @ x), TOL[prec], "yw")
         zw = to_host(plan.apply_TH(to_dev(u, dt), weighted=True))
-        assert rel(zw, T.conj().T @ (s * u)) < TOL[prec]
+        assert_close(zw, T.conj().T @ (s * u), TOL[prec], "zw")
     plan.destroy()
 
 
@@ -146,14 +146,14 @@ def test_apply_2d(gs, J, p, kind, M, prec):
     plan = gs.gs_plan(2, J, p, pts, mu, precision=prec)
     dt = torch.complex128 if prec == 0 else torch.complex64
     y = to_host(plan.apply_T(to_dev(X, dt)))
-    assert rel(y, basis.apply_T_2d(pts, J, p, X)) < TOL[prec]
+    assert_close(y, basis.apply_T_2d(pts, J, p, X), TOL[prec], "y")
     Z = to_host(plan.apply_TH(to_dev(u, dt)))
-    assert rel(Z, basis.apply_TH_2d(pts, J, p, u)) < TOL[prec]
+    assert_close(Z, basis.apply_TH_2d(pts, J, p, u), TOL[prec], "Z")
     s = np.sqrt(mu)
     yw = to_host(plan.apply_T(to_dev(X, dt), weighted=True))
-    assert rel(yw, s * basis.apply_T_2d(pts, J, p, X)) < TOL[prec]
+    assert_close(yw, s * basis.apply_T_2d(pts, J, p, X), TOL[prec], "yw")
     Zw = to_host(plan.apply_TH(to_dev(u, dt), weighted=True))
-    assert rel(Zw, basis.apply_TH_2d(pts, J, p, s * u)) < TOL[prec]
+    assert_close(Zw, basis.apply_TH_2d(pts, J, p, s * u), TOL[prec], "Zw")
     plan.destroy()
 
 
@@ -206,8 +206,8 @@ def test_mixed_plan_has_both_paths(gs):
     ref = basis.apply_T_2d(pts, 5, 2, X)
     y32 = to_host(plan.apply_T(to_dev(X, torch.complex64)))
     y64 = to_host(plan.apply_T(to_dev(X, torch.complex128), f64=True))
-    assert rel(y32, ref) < 2e-5
-    assert rel(y64, ref) < 1e-12
+    assert_close(y32, ref, 2e-5, "y32")
+    assert_close(y64, ref, 1e-12, "y64")
     plan32 = gs.gs_plan(2, 5, 2, pts, mu, precision=gs.GS_F32)
     with pytest.raises(gs.GSError):
         plan32.apply_T(to_dev(X, torch.complex128), f64=True)
@@ -239,8 +239,8 @@ def test_full_weight_adjoint(gs, dim, prec):
     x = crandn(rng, shape)
     got_adj = to_host(plan.apply_TH(to_dev(u, torch.complex128), weighted="full", f64=f64))
     got_fwd = to_host(plan.apply_T(to_dev(x, torch.complex128), weighted="full", f64=f64))
-    assert rel(got_adj.reshape(-1), T.conj().T @ (mu * u)) < 1e-12
-    assert rel(got_fwd, mu * (T @ x.reshape(-1))) < 1e-12
+    assert_close(got_adj.reshape(-1), T.conj().T @ (mu * u), 1e-12, "T^H W u")
+    assert_close(got_fwd, mu * (T @ x.reshape(-1)), 1e-12, "got_fwd")
     # the full-weight flag alone (without GS_WEIGHTED) is rejected
     import ctypes
     xin = to_dev(x, torch.complex128)

@@ -153,8 +153,14 @@ def test_deterministic_and_state_errors(gs):
     net.forward(u)
     with pytest.raises(gs.GSError):
         net.backward(t)
-    with pytest.raises(gs.GSError):
-        net.forward(to_dev(crandn(rng, (3, H, W)), torch.complex64))
+    x3 = to_dev(crandn(rng, (3, H, W)), torch.complex64)
+    with pytest.raises(ValueError):            # the binding refuses a batch above max_batch
+        net.forward(x3)
+    import ctypes
+    o3 = torch.empty_like(x3)                  # and so does the library itself
+    rc = gs.library().gs_cnn_forward(net.handle, ctypes.c_void_p(x3.data_ptr()), ctypes.c_void_p(o3.data_ptr()),
+                                     3, 0, None)
+    assert rc == gs.GS_ERR_INVALID_ARG
     net.destroy()
 
 

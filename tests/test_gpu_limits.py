@@ -5,17 +5,16 @@
   (2^20 coefficients, a 2^21-point grid on the four-step path) with 1,000,000
   random points (FP64: FP32 plans stop at J = 14, where a 32-bit position
   still has 17 bits of in-cell offset; 1D J = 14 in FP32 is the 65,536-point
-  workload's size, tested at full size elsewhere): T x on sampled rows and
-  T^H u on sampled coefficients (u supported on a seeded subset), against the
-  oracle's rows and columns;
+  workload's size, tested at full size elsewhere): T x on sampled rows, and
+  T^H u for a DENSE random u over all points on 32-34 sampled coefficients,
+  against values the oracle summed over every point
+  (tests/golden/make_dense_golden.py; inputs in tests/dense_cases.py);
 * the smallest grids: Haar at J = 1 (N = 2) in 1D and 2D, and the largest
   wavelet order p = 8 (at J = 4, where 2^J = 2p: no interior columns; and at
   J = 5), against the dense oracle.
-Tolerances: 1e-12 (FP64 applies), 2e-5 (FP32 applies).  Exception: a grid
-narrower than the window (n_g = 2N < W; in FP64, W = 14, so N <= 4 -- here
-N = 2) is wrapped by every window W / n_g times, so each grid value sums that
-many more rounded products; there the FP64 bound is 2e-12 (measured: up to
-1.1e-12 at N = 2, 2e-13 to 5e-13 elsewhere)."""
+Tolerances: 1e-12 (FP64 applies), 2e-5 (FP32 applies), norm-wise and for the
+worst element, with no exception for the smallest grids (the NFFT grid is never
+narrower than the window)."""
 import numpy as np
 import pytest
 
@@ -23,7 +22,9 @@ torch = pytest.importorskip("torch")
 
 from oracle import basis
 
-from gpu_util import crandn, rel, to_dev, to_host, say
+import dense_cases
+
+from gpu_util import assert_close, crandn, rel, to_dev, to_host, say
 
 pytestmark = pytest.mark.gpu
 
@@ -44,50 +45,36 @@ def _dt(f64):
 
 @pytest.mark.parametrize("f64", [True, False])
 def test_2d_largest_grid(gs, f64):
-    J, p, M = 11, 2, 100_000
-    N = 1 << J
+    c = dense_cases.case("limits_2d_J11")
+    J, p, pts = c["J"], c["p"], c["xi"]
+    M, N = pts.shape[0], 1 << J
     say(f"[limits 2D] J={J} M={M} f64={f64}")
     rng = np.random.default_rng(111)
-    pts = rng.uniform(-N, N, (M, 2))
     plan = gs.gs_plan(2, J, p, pts, None, precision=gs.GS_F32_MIXED)
     X = crandn(rng, (N, N))
     y = to_host(plan.apply_T(to_dev(X, _dt(f64)), f64=f64))
     rows = np.sort(rng.choice(M, 48, replace=False))
-    assert rel(y[rows], basis.rows_T_2d(pts, J, p, X, rows)) < TOL[f64]
-    support = np.sort(rng.choice(M, 20_000, replace=False))
-    u = np.zeros(M, dtype=np.complex128)
-    u[support] = crandn(rng, support.size)
-    Z = to_host(plan.apply_TH(to_dev(u, _dt(f64)), f64=f64))
-    ij = [(0, 0), (1, N - 1), (N - 1, 2), (N // 2, N // 2), (700, 1500), (N - 2, N - 2)]
-    want = []
-    for i, j in ij:
-        bi = basis.column_1d(pts[support, 0], J, p, i)
-        bj = basis.column_1d(pts[support, 1], J, p, j)
-        want.append(np.vdot(bi * bj, u[support]))
-    got = np.array([Z[i, j] for i, j in ij])
-    assert rel(got, np.array(want)) < TOL[f64]
+    assert_close(y[rows], basis.rows_T_2d(pts, J, p, X, rows), TOL[f64], "T x rows")
+    Z = to_host(plan.apply_TH(to_dev(c["u"], _dt(f64)), f64=f64))
+    ij = c["idx"]
+    assert_close(Z[ij[:, 0], ij[:, 1]], dense_cases.load_expected("limits_2d_J11"), TOL[f64], "T^H u samples")
     plan.destroy()
 
 
 def test_1d_largest_grid(gs):
-    J, p, M = 20, 4, 1_000_000
-    N = 1 << J
+    c = dense_cases.case("limits_1d_J20")
+    J, p, xi = c["J"], c["p"], c["xi"]
+    M, N = xi.size, 1 << J
     f64 = True
     say(f"[limits 1D] J={J} M={M}")
     rng = np.random.default_rng(112)
-    xi = rng.uniform(-N, N, M)
     plan = gs.gs_plan(1, J, p, xi, None, precision=gs.GS_F64)
     x = crandn(rng, N)
     y = to_host(plan.apply_T(to_dev(x, _dt(f64)), f64=f64))
     rows = np.sort(rng.choice(M, 12, replace=False))
-    assert rel(y[rows], basis.columns_1d(xi[rows], J, p).T @ x) < TOL[f64]
-    support = np.sort(rng.choice(M, 20_000, replace=False))
-    u = np.zeros(M, dtype=np.complex128)
-    u[support] = crandn(rng, support.size)
-    z = to_host(plan.apply_TH(to_dev(u, _dt(f64)), f64=f64))
-    idx = [0, 3, 4, 1000, N // 2, N - 5, N - 1]
-    want = np.array([np.vdot(basis.column_1d(xi[support], J, p, n), u[support]) for n in idx])
-    assert rel(z[idx], want) < TOL[f64]
+    assert_close(y[rows], basis.columns_1d(xi[rows], J, p).T @ x, TOL[f64], "T x rows")
+    z = to_host(plan.apply_TH(to_dev(c["u"], _dt(f64)), f64=f64))
+    assert_close(z[c["idx"]], dense_cases.load_expected("limits_1d_J20"), TOL[f64], "T^H u samples")
     plan.destroy()
 
 
@@ -107,9 +94,6 @@ def test_smallest_grids_and_largest_order(gs, dim, J, p, M, prec):
     y = to_host(plan.apply_T(to_dev(x, _dt(f64))))
     z = to_host(plan.apply_TH(to_dev(u, _dt(f64))))
     T = basis.dense_T_2d(xi, J, p) if dim == 2 else basis.dense_T_1d(xi, J, p)
-    ey, ez = rel(y, T @ x.reshape(-1)), rel(z.reshape(-1), T.conj().T @ u)
-    say(f"  T {ey:.2e}  T^H {ez:.2e}")
-    tol = 2e-12 if (f64 and 2 * N < 14) else TOL[f64]
-    assert ey < tol
-    assert ez < tol
+    assert_close(y, T @ x.reshape(-1), TOL[f64], "T x")
+    assert_close(z.reshape(-1), T.conj().T @ u, TOL[f64], "T^H u")
     plan.destroy()

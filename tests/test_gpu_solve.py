@@ -8,7 +8,7 @@ from oracle import basis, lsq
 from workloads import config_c1, complex_noise, spiral_2d, jitter_2d, voronoi_weights_2d, ellipse_phantom_params, \
     phantom_cell_averages
 
-from gpu_util import rel, crandn, to_dev, to_host, say
+from gpu_util import assert_close, rel, crandn, to_dev, to_host, say
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +34,7 @@ def test_c1_solve_matches_lstsq(gs):
     x, info = plan.solve(to_dev(y, torch.complex128), rel_tol=c["tol"], max_iter=500, history=True)
     assert info["status"] == gs.GS_OK
     assert info["rel_residual"] <= c["tol"]
-    assert rel(to_host(x), x_ref) < 1e-6
+    assert_close(to_host(x), x_ref, 1e-6, "x")
     assert len(info["history"]) == info["iterations"] + 1
     # the same recurrence on the oracle's dense matrices
     _, it_ref, _ = lsq.cgls(lambda v: T @ v, lambda v: T.conj().T @ v, y, np.zeros(256, complex), c["tol"], 500)
@@ -59,8 +59,12 @@ def _small_2d(J=5, p=4, pattern="spiral", seed=301):
     return pts, mu, x0
 
 
-@pytest.mark.parametrize("pattern,prec", [("spiral", 0), ("jitter", 0), ("jitter", 2)])
+@pytest.mark.parametrize("pattern,prec", [("spiral", 0), ("jitter", 0), ("jitter", 2), ("spiral", 2)])
 def test_2d_weighted_solve_matches_lstsq(gs, pattern, prec):
+    """Plain FP64 and FP32-mixed solves to a normal residual of 1e-10 are
+    within 1e-6 of the oracle's weighted LS solution, element by element.  The
+    mixed form reaches 1e-10 through its FP64 refinement restarts (each one
+    gains about the FP32 accuracy on the remaining error)."""
     say(f"[2d solve] {pattern} prec={prec}")
     J, p = 5, 4
     pts, mu, x0 = _small_2d(J, p, pattern)
@@ -69,20 +73,39 @@ def test_2d_weighted_solve_matches_lstsq(gs, pattern, prec):
     y = y + complex_noise(y.size, 1e-4 * np.linalg.norm(y) / np.sqrt(2 * y.size), 302)
     x_ref = lsq.lstsq_dense(T, y, mu).reshape(32, 32)
     plan = gs.gs_plan(2, J, p, pts, mu, precision=prec)
-    tol = 1e-10 if prec == 0 else 1e-6
-    x, info = plan.solve(to_dev(y, torch.complex128), rel_tol=tol, max_iter=400, refine_fp64=True, max_restarts=3)
-    err = rel(to_host(x), x_ref)
+    tol = 1e-10
+    x, info = plan.solve(to_dev(y, torch.complex128), rel_tol=tol, max_iter=1000, refine_fp64=True,
+                         max_restarts=8)
     say(f"  iters={info['iterations']} restarts={info['restarts']} rr={info['rel_residual']:.2e} "
-        f"rr64={info['rel_residual_fp64']:.2e} err={err:.2e}")
-    if prec == 0:
-        assert info["status"] == gs.GS_OK and err < 1e-6
-    else:
-        # FP32 applies + FP64 refinement: the FP64-recomputed normal residual
-        # meets the tolerance; with condition ~3 the iterate is within
-        # kappa^2 * tol of the LS solution
-        assert info["status"] == gs.GS_OK
+        f"rr64={info['rel_residual_fp64']:.2e}")
+    assert info["status"] == gs.GS_OK
+    if prec == 2:
         assert info["rel_residual_fp64"] <= tol
-        assert err < 1e-4
+    assert_close(to_host(x), x_ref, 1e-6, "x vs oracle LS")
+    plan.destroy()
+
+
+def test_f32_plan_below_its_floor(gs):
+    """A plain FP32 plan asked for a tolerance below FP32 accuracy on
+    inconsistent data: the recurrence stalls, which is a stop, not a
+    breakdown.  The status is GS_NOT_CONVERGED and x is the run's best
+    iterate: finite, with a small true (oracle) normal residual."""
+    say("[f32 floor]")
+    J, p = 5, 2
+    pts, mu, _ = _small_2d(J, p, "jitter")
+    y = crandn(np.random.default_rng(78), pts.shape[0])
+    plan = gs.gs_plan(2, J, p, pts, mu, precision=gs.GS_F32)
+    x, info = plan.solve(to_dev(y, torch.complex128), rel_tol=1e-12, max_iter=600)
+    xh = to_host(x).reshape(-1)
+    T = basis.dense_T_2d(pts, J, p)
+    w = mu
+    g0 = np.linalg.norm(T.conj().T @ (w * y))
+    g = np.linalg.norm(T.conj().T @ (w * (y - T @ xh)))
+    say(f"  status={info['status']} iters={info['iterations']} rr={info['rel_residual']:.2e} true={g / g0:.2e}")
+    assert info["status"] == gs.GS_NOT_CONVERGED
+    assert info["iterations"] < 600
+    assert np.isfinite(xh).all()
+    assert g / g0 < 1e-4
     plan.destroy()
 
 
@@ -99,7 +122,7 @@ def test_warm_start_and_limits(gs):
     x_warm, info_warm = plan.solve(yd, xw, rel_tol=1e-8, max_iter=300, warm_start=True)
     assert info_warm["status"] == gs.GS_OK and info_cold["status"] == gs.GS_OK
     assert info_warm["iterations"] < info_cold["iterations"]
-    assert rel(to_host(x_warm), to_host(x_cold)) < 1e-6
+    assert_close(to_host(x_warm), to_host(x_cold), 1e-6, "x_warm")
     # max_iter reached -> positive status, x holds the last iterate
     x1, info1 = plan.solve(yd, rel_tol=1e-14, max_iter=1)
     assert info1["status"] == gs.GS_NOT_CONVERGED and info1["iterations"] == 1

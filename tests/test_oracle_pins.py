@@ -343,6 +343,11 @@ def test_single_column_matches_all_columns(p):
     B = basis.columns_1d(xi, J, p)
     for n in (0, 1, p - 1, p, 16, 31 - p, 31 - p + 1, 31):
         assert np.array_equal(basis.column_1d(xi, J, p, n), B[n])
+    ns = [0, p - 1, p, 16, 31 - p, 31]
+    sub = basis.columns_subset_1d(xi, J, p, ns)
+    assert sorted(sub) == sorted(set(ns))
+    for n in ns:
+        assert np.array_equal(sub[n], B[n])
 
 
 # ------------------------------------------------------------------ NDFT (O5)
