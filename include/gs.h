@@ -52,6 +52,7 @@ extern "C" {
 #define GS_ERR_HIP         (-5) /* HIP runtime error (text via gs_strerror)       */
 #define GS_ERR_BREAKDOWN   (-6) /* CGLS breakdown: ||A p||^2 <= 0 or non-finite  */
 #define GS_ERR_PRECISION   (-7) /* requested precision not held by this plan     */
+#define GS_ERR_TOO_LARGE   (-8) /* gs_apply_TH_noalloc: workspace above its limit */
 
 /* plan precision */
 #define GS_F64        0  /* applies in FP64, complex128 vectors                       */
@@ -110,6 +111,28 @@ int gs_apply_T(const gs_plan_t* plan, const void* x, void* y, int flags, void* s
  * repeated calls give bitwise-identical results (no atomics).
  */
 int gs_apply_TH(const gs_plan_t* plan, const void* u, void* x, int flags, void* stream);
+
+/*
+ * gs_apply_TH_noalloc -- gs_apply_TH (same operation, arguments, flags,
+ * layouts, element types and results, bit for bit) for callers that cannot
+ * allocate device memory or call allocating routines: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  It calls no
+ * hipMalloc, hipFree or allocating library routine.  Its transform workspace
+ * (the oversampled grid, the 2D side grids, the tile partial sums and the
+ * input in sorted order) is carved from one static device array of
+ * GS_NOALLOC_SCRATCH_BYTES (64 MiB) per device, which each device holds until
+ * the process ends; the plan's own workspace is not touched.  The workspace
+ * grows with the grid (n_g^dim complex), the tiles (about 2,900 complex per
+ * 32 x 32-cell tile in 2D) and the points (M complex): about 39 MB for the
+ * 1,048,576-point J = 9 problem in FP32 (78 MB in FP64, which is refused).
+ * A plan whose workspace exceeds the array returns GS_ERR_TOO_LARGE before
+ * any device work.  The array is shared by every call on a device and keeps
+ * the last call's contents: calls that overlap on one device (on different
+ * streams, or from several host threads) race and must be serialized by the
+ * caller.  The first call on a device looks up the array's device address.
+ */
+#define GS_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int gs_apply_TH_noalloc(const gs_plan_t* plan, const void* u, void* x, int flags, void* stream);
 
 /* CGLS options / results (Sec. 2: conjugate gradients on the LS problem). */
 typedef struct gs_solve_opts {

@@ -227,6 +227,7 @@ const char* gs_strerror(int code) {
         case GS_ERR_HIP: return g_hip_msg[0] ? g_hip_msg : "HIP runtime error";
         case GS_ERR_BREAKDOWN: return "CGLS breakdown (||A p||^2 <= 0 or non-finite)";
         case GS_ERR_PRECISION: return "requested precision is not held by this plan";
+        case GS_ERR_TOO_LARGE: return "the apply needs more workspace than the static device array holds";
         default: return "unknown status";
     }
 }
@@ -409,6 +410,90 @@ int gs_apply_TH(const gs_plan_t* plan, const void* u, void* x, int flags, void* 
                          : gs::launch_apply_TH<float>(plan->impl, (const gs::cx<float>*)u, (gs::cx<float>*)x, flags,
                                                       (hipStream_t)stream);
     return e == hipSuccess ? GS_OK : hip_fail(e);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free adjoint
+//
+// gs_apply_TH_noalloc runs the adjoint's kernels on a workspace carved from
+// one file-scope device array instead of the plan's own buffers.  Each device
+// holds its own copy of the array; its device address is looked up once per
+// device (with that device current) and cached.  Nothing in the array needs
+// to start at zero: every kernel writes each workspace element before any
+// kernel reads it (tile partials are written whole, empty tiles as zeros).
+static __device__ __align__(256) unsigned char scratch[GS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};   // per device: device address of `scratch`
+
+int scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    if (dev < 0 || dev >= kMaxDevices) return GS_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e);
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return GS_OK;
+}
+
+// Lays the adjoint workspace of plan P (precision T) out from `base` in
+// 256-byte aligned pieces; returns the bytes it spans.  With base == 0 only
+// the size is computed.
+template <class T>
+size_t carve_work(const gs::Plan& P, uintptr_t base, gs::Work<T>* w) {
+    using C = gs::cx<T>;
+    size_t off = 0;
+    auto take = [&](size_t elems) -> C* {
+        C* ptr = base ? reinterpret_cast<C*>(base + off) : nullptr;
+        off += (elems * sizeof(C) + 255) & ~size_t(255);
+        return ptr;
+    };
+    const size_t gsz = P.dim == 2 ? (size_t)P.ng * P.ng : (size_t)P.ng;
+    gs::Work<T> r;
+    r.grid = take(gsz);
+    if (P.dim == 2 && P.nb) {
+        r.sr = take((size_t)2 * P.nb * P.ng);
+        r.sc = take((size_t)2 * P.nb * P.ng);
+    }
+    r.part = take(gs::adjoint_part_elems(P.dim, P.M, P.nb, P.ng));
+    r.vbuf = take((size_t)P.M);
+    if (w) *w = r;
+    return off;
+}
+
+template <class T>
+int apply_TH_static(const gs::Plan& P, const void* u, void* x, int flags, hipStream_t s) {
+    const size_t need = carve_work<T>(P, 0, nullptr);
+    if (need > (size_t)GS_NOALLOC_SCRATCH_BYTES) return GS_ERR_TOO_LARGE;
+    void* base = nullptr;
+    int rc = scratch_address(&base);
+    if (rc) return rc;
+    gs::Work<T> w;
+    carve_work<T>(P, reinterpret_cast<uintptr_t>(base), &w);
+    hipError_t e = gs::launch_apply_TH<T>(P, (const gs::cx<T>*)u, (gs::cx<T>*)x, flags, s, &w);
+    return e == hipSuccess ? GS_OK : hip_fail(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+int gs_apply_TH_noalloc(const gs_plan_t* plan, const void* u, void* x, int flags, void* stream) {
+    bool use64 = false;
+    int rc = pick_apply(plan, u, x, flags, use64);
+    if (rc) return rc;
+    return use64 ? apply_TH_static<double>(plan->impl, u, x, flags, (hipStream_t)stream)
+                 : apply_TH_static<float>(plan->impl, u, x, flags, (hipStream_t)stream);
 }
 
 int gs_get_plan_info(const gs_plan_t* plan, gs_plan_info* info) {

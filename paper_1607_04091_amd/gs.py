@@ -24,6 +24,8 @@ GS_ERR_NOMEM = -4
 GS_ERR_HIP = -5
 GS_ERR_BREAKDOWN = -6
 GS_ERR_PRECISION = -7
+GS_ERR_TOO_LARGE = -8
+GS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 GS_F64, GS_F32, GS_F32_MIXED = 0, 1, 2
 GS_WEIGHTED, GS_SORTED, GS_APPLY_F64, GS_WEIGHT_FULL = 1, 2, 4, 8
@@ -36,7 +38,7 @@ def _wflags(weighted):
     return GS_WEIGHTED if weighted else 0
 
 EXPORTS = [
-    "gs_plan", "gs_apply_T", "gs_apply_TH", "gs_solve", "gs_solve_batch", "gs_destroy", "gs_get_plan_info",
+    "gs_plan", "gs_apply_T", "gs_apply_TH", "gs_apply_TH_noalloc", "gs_solve", "gs_solve_batch", "gs_destroy", "gs_get_plan_info",
     "gs_get_permutation", "gs_strerror", "gs_version", "gs_filter_taps", "gs_boundary_filters",
     "gs_eval_basis_1d", "gs_profile_enable", "gs_profile_read",
     "gs_cnn_param_count", "gs_cnn_create", "gs_cnn_destroy", "gs_cnn_set_weights", "gs_cnn_get_weights",
@@ -83,6 +85,7 @@ def _load():
     lib.gs_plan.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i64, dp, dp, i32, vp]
     lib.gs_apply_T.argtypes = [vp, vp, vp, i32, vp]
     lib.gs_apply_TH.argtypes = [vp, vp, vp, i32, vp]
+    lib.gs_apply_TH_noalloc.argtypes = [vp, vp, vp, i32, vp]
     lib.gs_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
     lib.gs_solve_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                    ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), i32, vp]
@@ -302,6 +305,19 @@ class Plan:
                               _stream(stream))
         if rc:
             raise GSError(rc, "gs_apply_TH")
+        return x
+
+    def apply_TH_noalloc(self, u, x, weighted=False, sorted_order=False, f64=False, stream=None):
+        """gs_apply_TH_noalloc: the adjoint on the library's static device
+        workspace; x (the output) must be supplied."""
+        dt = self._dtype(f64)
+        _check_vec(u, dt, self.M, "u")
+        _check_vec(x, dt, self.N ** self.dim, "x", like=u)
+        flags = _wflags(weighted) | (GS_SORTED if sorted_order else 0) | (GS_APPLY_F64 if f64 else 0)
+        rc = _lib.gs_apply_TH_noalloc(self.handle, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                      flags, _stream(stream))
+        if rc:
+            raise GSError(rc, "gs_apply_TH_noalloc")
         return x
 
     def solve(self, y, x=None, rel_tol=1e-6, max_iter=500, warm_start=False, refine_fp64=True, max_restarts=2,

@@ -32,7 +32,7 @@ def test_exports_every_declared_symbol():
 
 def test_version_and_strerror():
     assert gs.gs_version() == 100
-    for code in (0, 1, -1, -2, -3, -4, -5, -6, -7):
+    for code in (0, 1, -1, -2, -3, -4, -5, -6, -7, -8):
         assert len(gs.strerror(code)) > 3
     assert "unknown" in gs.strerror(1234)
 
