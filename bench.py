@@ -94,14 +94,108 @@ def oracle_baseline(pts, mu, J, p, sample, M):
     Z = basis.apply_TH_2d(P, J, p, s * u)
     t = time.perf_counter() - t0
     assert np.isfinite(y).all() and np.isfinite(Z).all()
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count()
+    cores = _blas_threads()
     return {"value": 1.0 / (t * M / sample), "unit": "pairs/s", "cores": int(cores), "kind": "oracle",
             "sample": f"one weighted T and one T^H over {sample} of the {M} points (FP64, dense per-dimension "
                       f"columns + BLAS), {t:.2f} s, scaled linearly to all points"}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        return os.cpu_count()
+
+
+def oracle_workloads(args, gpu_c1):
+    """The oracle timed at the other workloads (FP64, all BLAS threads):
+    one weighted apply pair at C1 (1D db2, J = 8, 1024 points k/2, whole),
+    C2 (1D db4, J = 14, 65,536 jittered points; a seeded sample, scaled to all
+    points) and C5 (2D db4, J = 8, 262,144 spiral points; a sample, scaled);
+    the C1 least-squares solve (LAPACK lstsq on the dense T) on data the oracle
+    forms itself; the C2 CGLS time extrapolated from the pair time and the
+    GPU's iteration count (a full dense C2 CGLS takes tens of minutes)."""
+    from oracle import basis, lsq
+    from workloads import config_c1, config_c2, config_c5_pattern, complex_noise
+    out = {}
+    rng = np.random.default_rng(3)
+
+    def pair_1d(xi, mu, J, p, x, u):
+        s = np.sqrt(mu) if mu is not None else 1.0
+        t0 = time.perf_counter()
+        y = s * basis.apply_T_1d(xi, J, p, x, chunk=2048)
+        z = basis.apply_TH_1d(xi, J, p, s * u, chunk=2048)
+        t = time.perf_counter() - t0
+        assert np.isfinite(y).all() and np.isfinite(z).all()
+        return t
+
+    c1 = config_c1()
+    t = pair_1d(c1["xi"], None, c1["J"], c1["p"], c1["x0"], rng.standard_normal(c1["xi"].size) + 0j)
+    T = basis.dense_T_1d(c1["xi"], c1["J"], c1["p"])
+    y = T @ c1["x0"] + complex_noise(c1["xi"].size, c1["noise_sigma"], c1["noise_seed"])
+    t0 = time.perf_counter()
+    x_ls = lsq.lstsq_dense(T, y)
+    t_ls = time.perf_counter() - t0
+    out["c1"] = {"pairs_per_s": round(1.0 / t, 2), "sample": "all 1024 points", "lstsq_s": round(t_ls, 4)}
+    if gpu_c1 is not None:
+        out["c1"]["gpu_solution_vs_oracle_lstsq"] = float(np.linalg.norm(gpu_c1 - x_ls) / np.linalg.norm(x_ls))
+
+    c2 = config_c2()
+    n2 = min(args.cpu_sample // 8, c2["xi"].size)
+    idx = np.sort(rng.choice(c2["xi"].size, n2, replace=False))
+    t = pair_1d(c2["xi"][idx], c2["mu"][idx], c2["J"], c2["p"], c2["x0"], rng.standard_normal(n2) + 0j)
+    t_full = t * c2["xi"].size / n2
+    out["c2"] = {"pairs_per_s": round(1.0 / t_full, 5), "sample": f"{n2} of {c2['xi'].size} points, "
+                 f"{t:.2f} s, scaled linearly", "pair_s": round(t_full, 2)}
+
+    c5 = config_c5_pattern(with_weights=False)
+    pts = c5["xi"]
+    n5 = min(args.cpu_sample, pts.shape[0])
+    idx = np.sort(rng.choice(pts.shape[0], n5, replace=False))
+    N5 = 1 << c5["J"]
+    X = rng.standard_normal((N5, N5)) + 1j * rng.standard_normal((N5, N5))
+    t0 = time.perf_counter()
+    yy = basis.apply_T_2d(pts[idx], c5["J"], c5["p"], X)
+    zz = basis.apply_TH_2d(pts[idx], c5["J"], c5["p"], rng.standard_normal(n5) + 0j)
+    t = time.perf_counter() - t0
+    assert np.isfinite(yy).all() and np.isfinite(zz).all()
+    out["c5"] = {"pairs_per_s": round(n5 / (t * pts.shape[0]), 4),
+                 "sample": f"{n5} of {pts.shape[0]} points, {t:.2f} s, scaled linearly"}
+    return out
+
+
+def c1_solve(gs, torch, dev):
+    """The 1D uniform workload (db2, J = 8, 1024 frequencies k/2, unit weights):
+    the plan takes the exact uniform-node path (Sec. 3.2); y = T x0 by the
+    library's FP64 apply plus 1e-8 complex noise; CGLS to 1e-10 (FP64)."""
+    from workloads import config_c1, complex_noise
+    c = config_c1()
+    pl = gs.gs_plan(1, c["J"], c["p"], c["xi"], None, precision=gs.GS_F64)
+    exact = pl.info()["exact_nodes"]
+    x0 = torch.from_numpy(c["x0"]).to(dev)
+    y = pl.apply_T(x0) + torch.from_numpy(complex_noise(c["xi"].size, c["noise_sigma"], c["noise_seed"])).to(dev)
+    pl.solve(y, rel_tol=c["tol"], max_iter=2)                       # warm-up of the code path
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info = pl.solve(y, rel_tol=c["tol"], max_iter=500, check_every=10)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pl.destroy()
+    log(f"[bench] C1 solve (exact nodes: {exact}): {dt * 1e3:.2f} ms, {info['iterations']} iterations")
+    return {"wall_s": round(dt, 5), "iterations": info["iterations"], "status": info["status"],
+            "rel_residual": info["rel_residual"], "exact_nodes": bool(exact)}, x.cpu().numpy()
 
 
 def batch_c4(gs, torch, dev, n_problems):
@@ -524,6 +618,7 @@ def main():
                  "ceiling_pairs_per_s": round(HBM_PEAK_GBS * 1e9 / pb, 1)}
 
     solve = {}
+    c1_x = None
     if not args.no_solve:
         x0d = torch.from_numpy(x0).to(dev)
         yclean = torch.empty(M, dtype=torch.complex128, device=dev)
@@ -555,6 +650,7 @@ def main():
         solve["fp32_mixed"]["rel_diff_vs_plain_fp64"] = d / torch.linalg.vector_norm(sols["plain_fp64"]).item()
         log(f"[bench] mixed vs plain FP64 solution: {solve['fp32_mixed']['rel_diff_vs_plain_fp64']:.2e}")
         solve["warm_start"] = None
+        solve["c1_1d"], c1_x = c1_solve(gs, torch, dev)
         solve["c2_1d"] = c2_solves(gs, torch, dev)
         if not args.no_batch:
             solve["batched_c4"] = batch_c4(gs, torch, dev, args.batch_problems)
@@ -569,6 +665,14 @@ def main():
     if not args.no_cpu:
         cpu = oracle_baseline(pts, mu, J, p, min(args.cpu_sample, M), M)
         log(f"[bench] oracle: {cpu['value']:.3e} pairs/s on {cpu['cores']} threads")
+        cpu["cpu_model"] = _cpu_model()
+        cpu["host_cpus"] = os.cpu_count()
+        cpu["workloads"] = oracle_workloads(args, c1_x)
+        c2_it = (solve.get("c2_1d") or {}).get("fp64", {}).get("iterations")
+        if c2_it:
+            cpu["workloads"]["c2"]["cgls_s_extrapolated"] = round(cpu["workloads"]["c2"]["pair_s"] * c2_it, 1)
+            cpu["workloads"]["c2"]["cgls_iterations_assumed"] = c2_it
+        log(f"[bench] oracle workloads: {json.dumps(cpu['workloads'])}")
 
     line = {
         "metric": "T+T^H apply pairs/s (2D 512², 1M pts); time-to-rel-res 1e-6 plain vs warm-start",

@@ -87,6 +87,12 @@ typedef struct gs_plan gs_plan_t;
  *              App. B), or NULL for unit weights.
  *   precision  GS_F64, GS_F32 or GS_F32_MIXED.
  *   stream     stream for the uploads.
+ * Uniform nodes (Sec. 3.2): when every frequency lies on a grid eps Z with
+ * eps = 2^-a, a <= 3 (e.g. xi_k = k/2), every wrapped node is a node of an
+ * oversampled grid of side max(2N, 2^a N); the interior block is then computed
+ * exactly -- a zero-padded FFT read at the nodes, the paper's phase-shifted,
+ * zero-interleaved DFT -- with no window error and no deapodization
+ * (gs_plan_info.exact_nodes reports it).  Other node sets use the windowed NFFT.
  * Host inputs are copied; the caller may free them on return.  The plan owns
  * all of its device memory (point data, transform grids, solver vectors).
  * A plan is not thread-safe: calls on one plan share its workspace and must
@@ -207,6 +213,8 @@ typedef struct gs_plan_info {
     int     window_w32;      /* KB window taps per dimension, FP32 path (0 if absent) */
     int     window_w64;      /* KB window taps per dimension, FP64 path (0 if absent) */
     int64_t device_bytes;    /* device memory held by the plan */
+    int     exact_nodes;     /* 1: every frequency lies on a grid 2^-a Z (a <= 3) and the
+                                transform is exact (Sec. 3.2 uniform nodes), see gs_plan */
 } gs_plan_info;
 int gs_get_plan_info(const gs_plan_t* plan, gs_plan_info* info);
 

@@ -82,6 +82,18 @@ int hw_threads() {
     return n == 0 ? 4 : (int)std::min(n, 64u);
 }
 
+// Smallest a in 0..3 such that every value times 2^a is an integer (all
+// frequencies lie on the grid 2^-a Z), or -1.
+int uniform_level(const double* v, int64_t n) {
+    int a = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(std::fabs(v[i]) < 0x1p50)) return -1;
+        while (a <= 3 && std::ldexp(v[i], a) != std::floor(std::ldexp(v[i], a))) ++a;
+        if (a > 3) return -1;
+    }
+    return a;
+}
+
 uint64_t fixed_point_frac(double xi, int J) {
     const double eta = std::ldexp(xi, -J);
     const double f = eta - std::floor(eta);   // exact, in [0, 1)
@@ -123,11 +135,20 @@ hipError_t upload_prec(gs::Plan& P, const HostPoints& H, const std::vector<doubl
         for (size_t q = 0; q < M; ++q) hs[q] = (T)smu_sorted[q];
         GS_HIP_TRY(hipMemcpy(d.smu, hs.data(), M * sizeof(T), hipMemcpyHostToDevice));
     }
-    // window and deapodization
+    // window and deapodization.  On exact nodes (P.exact) the window is the
+    // linear hat, which at a node has the taps (.., 0, 1, 0, ..): interpolation
+    // and spreading then read and write the node itself, with no window error,
+    // and no deapodization is needed.
     const KBWindow kb = make_window(w, deg, beta);
     {
-        GS_HIP_TRY(dalloc(P, d.win, kb.coef.size()));
         std::vector<T> hw(kb.coef.begin(), kb.coef.end());
+        if (P.exact) {
+            std::fill(hw.begin(), hw.end(), T(0));
+            const int j0 = w / 2 - 1, n = deg + 1;   // taps at distance t and t - 1
+            hw[j0 * n] = T(0.5); hw[j0 * n + 1] = T(-0.5);
+            hw[(j0 + 1) * n] = T(0.5); hw[(j0 + 1) * n + 1] = T(0.5);
+        }
+        GS_HIP_TRY(dalloc(P, d.win, hw.size()));
         GS_HIP_TRY(hipMemcpy(d.win, hw.data(), hw.size() * sizeof(T), hipMemcpyHostToDevice));
     }
     {
@@ -135,7 +156,7 @@ hipError_t upload_prec(gs::Plan& P, const HostPoints& H, const std::vector<doubl
         std::vector<T> hd(P.N);
         for (int j = 0; j < P.N; ++j) {
             const bool interior = j >= P.nb && j < P.N - P.nb;
-            hd[j] = interior ? (T)(1.0 / kb.ft((double)(j - P.N / 2) / P.ng)) : T(0);
+            hd[j] = !interior ? T(0) : P.exact ? T(1) : (T)(1.0 / kb.ft((double)(j - P.N / 2) / P.ng));
         }
         GS_HIP_TRY(hipMemcpy(d.deap, hd.data(), hd.size() * sizeof(T), hipMemcpyHostToDevice));
     }
@@ -261,7 +282,19 @@ int gs_plan(gs_plan_t** out, int dim, int J, int p, int64_t M, const double* xi,
     // oversampling 2, except that the grid is never narrower than 16 cells:
     // every window (at most 14 taps) then covers distinct cells, so each grid
     // value enters a sum once (a wrapped window would sum it several times)
-    P.ng = std::max(2 * P.N, gs::MIN_GRID); P.G = gs::ilog2(P.ng);
+    P.ng = std::max(2 * P.N, gs::MIN_GRID);
+    // Uniform nodes (Sec. 3.2): frequencies on a grid eps Z, eps = 2^-a, are
+    // nodes of a grid of side N 2^a; on such nodes the transform is exact
+    // (a zero-padded FFT read at the nodes, no window error)
+    {
+        const int a = uniform_level(xi, M * dim);
+        const int64_t ng_max = dim == 2 ? 4096 : (int64_t)1 << 21;
+        if (a >= 0 && std::max<int64_t>(P.ng, (int64_t)P.N << a) <= ng_max) {
+            P.exact = true;
+            P.ng = std::max(P.ng, P.N << a);
+        }
+    }
+    P.G = gs::ilog2(P.ng);
     if (dim == 1 && P.ng > gs::FFT_MAX_LDS) {
         P.lg1 = P.G / 2; P.lg2 = P.G - P.lg1;
     } else {
@@ -504,6 +537,7 @@ int gs_get_plan_info(const gs_plan_t* plan, gs_plan_info* info) {
     info->window_w32 = P.d32.present ? P.d32.w : 0;
     info->window_w64 = P.d64.present ? P.d64.w : 0;
     info->device_bytes = P.bytes;
+    info->exact_nodes = P.exact ? 1 : 0;
     return GS_OK;
 }
 

@@ -82,6 +82,7 @@ struct Plan {
     int dim = 0, J = 0, p = 0, nb = 0, N = 0, precision = 0;
     int64_t M = 0;
     int ng = 0, G = 0;              // grid size per dim and log2
+    bool exact = false;             // every node is a grid node: hat window, no deapodization
     int ts = 0;                     // 2D tile side in cells (min(TILE, ng))
     int n1 = 0, n2 = 0, lg1 = 0, lg2 = 0;   // four-step split (1D, ng > FFT_MAX_LDS)
     int cr1 = 0, cr2 = 0;           // 2D column transform split ng = cr1 * cr2 (0: natural row order);

@@ -9,9 +9,10 @@
 // tile's grid window (TS+W-1 squared) in LDS, interpolates the interior,
 // adds the boundary part and applies D_x D_y and sqrt(mu).
 //
-// Adjoint: adj_gather_kernel brings the (weighted) input into sorted order.
-// Two tile kernels then read the tile's points in chunks staged in LDS
-// (window taps and channel products, computed once per point):
+// Adjoint: input in caller order is first gathered into sorted order and
+// weighted (adj_gather_kernel; sorted input is weighted on the way in).  Two
+// tile kernels then read the tile's points in chunks staged in LDS (window
+// taps and channel products computed once per point):
 //   * adj_interior_kernel: column-owner threads (one per padded output column
 //     and block of cell rows) gather the interior 2D spread into register
 //     accumulators, plus the row-side (x-boundary) channels;
@@ -81,6 +82,7 @@ __device__ inline void taps_all(T t, const T* __restrict__ coef, T* w) {
 }
 
 constexpr int TILE_TS = 32;     // grid cells per tile side
+static_assert(TILE_TS == TILE, "tile side of the plan's sort");
 constexpr int TILE_RB = 8;      // cell rows per column-owner block
 // threads of the forward tile kernels, which loop over the tile's points: one
 // point per thread on average in FP32, so that grids of few tiles (one
@@ -265,11 +267,22 @@ __device__ inline int rb_point(const int* off, int k, int s) {   // tile-relativ
     return p < off[(b + 1) * RB * TS] ? p : -1;
 }
 
+// Adjoint input of sorted point q, read by the tile kernels: u in sorted
+// order, times the weight factor of a weighted apply.  Input in caller order
+// is first gathered into sorted order by adj_gather_kernel (a random gather
+// inside the tile kernels' chunk loads measured slower than the extra pass).
+template <class T>
+__device__ inline cx<T> adj_input(const TileGeo<T>& g, const cx<T>* __restrict__ u, int flags, int q) {
+    cx<T> v = u[q];
+    if (flags & GS_WEIGHTED) v = cscale(v, wscale(g.smu[q], flags));
+    return v;
+}
+
 template <class T>
 __global__ void adj_gather_kernel(TileGeo<T> g, const cx<T>* __restrict__ u, int flags, cx<T>* __restrict__ vs) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= g.M) return;
-    cx<T> v = u[(flags & GS_SORTED) ? q : g.perm[q]];
+    cx<T> v = u[g.perm[q]];
     if (flags & GS_WEIGHTED) v = cscale(v, wscale(g.smu[q], flags));
     vs[q] = v;
 }
@@ -349,7 +362,7 @@ struct IntPre {
 // column lies in [ply-W+1, ply], reading each point once per column.  The
 // global loads of chunk k+1 are issued before chunk k is gathered.
 template <class T, int W, int DEG, int NB>
-__global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(TileGeo<T> g, const cx<T>* __restrict__ vs,
+__global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(TileGeo<T> g, const cx<T>* __restrict__ u, int flags,
                                                                             cx<T>* __restrict__ partI,
                                                                             cx<T>* __restrict__ partR) {
     using L = AdjIntLDS<T, W, NB>;
@@ -381,7 +394,7 @@ __global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(Tile
         const int q = q0 + pre.p;
         pre.px = g.pos[q];
         pre.py = g.pos[M + q];
-        pre.v = vs[q];
+        pre.v = adj_input(g, u, flags, q);
         pre.dx = g.chx[NB * M + q];
         pre.dy = g.chy[NB * M + q];
 #pragma unroll
@@ -530,7 +543,7 @@ struct BndPre {
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 template <class T, int W, int DEG, int NB, int BL>
-__global__ void __launch_bounds__(BND_THREADS) __attribute__((amdgpu_waves_per_eu(2))) adj_boundary_kernel(TileGeo<T> g, const cx<T>* __restrict__ vs,
+__global__ void __launch_bounds__(BND_THREADS) __attribute__((amdgpu_waves_per_eu(2))) adj_boundary_kernel(TileGeo<T> g, const cx<T>* __restrict__ u, int flags,
                                                                    cx<T>* __restrict__ partC, cx<T>* __restrict__ partX) {
     using L = AdjBndLDS<T, W, NB, BL>;
     constexpr int TS = TILE_TS, RB = ADJ_RB, PW = L::PW, NRB = L::NRB, NCH = L::NCH, NE = L::NE;
@@ -589,7 +602,7 @@ __global__ void __launch_bounds__(BND_THREADS) __attribute__((amdgpu_waves_per_e
             if (pre[j].p < 0) continue;
             const int q = q0 + pre[j].p;
             const bool xh = (h & 1) == 0;
-            pre[j].v = vs[q];
+            pre[j].v = adj_input(g, u, flags, q);
             if (xh)
                 pre[j].px = gpos[q];
             else
@@ -860,10 +873,12 @@ hipError_t adjoint2d_tile_nb(const Plan& P, const cx<T>* u, cx<T>* x, int flags,
     cx<T>* partR = partI + (size_t)nt * PW * PW;
     cx<T>* partC = partR + (size_t)nt * nch * PW;
     cx<T>* partX = partC + (size_t)nt * nch * PW;
-    {
+    if (!(flags & GS_SORTED)) {
         ProfScope _p(K_ADJ_PREP, s);
         hipLaunchKernelGGL((adj_gather_kernel<T>), dim3((P.M + 255) / 256), dim3(256), 0, s, g, u, flags, d.vbuf);
         GS_HIP_TRY(hipGetLastError());
+        u = d.vbuf;
+        flags = GS_SORTED;   // gathered and weighted
     }
     // The interior and the column-side/corner kernels read the same staged
     // input and write disjoint partials.  The second runs on the plan's side
@@ -884,16 +899,16 @@ hipError_t adjoint2d_tile_nb(const Plan& P, const cx<T>* u, cx<T>* x, int flags,
         ProfScope _p(K_BND2D, s2);
         if (std::is_same<T, float>::value && nt > 256)
             hipLaunchKernelGGL((adj_boundary_kernel<T, W, DEG, NB, std::is_same<T, float>::value ? BND_LDS_FOUR : BND_LDS>),
-                               dim3(nt), dim3(BND_THREADS), 0, s2, g, (const cx<T>*)d.vbuf, partC, partX);
+                               dim3(nt), dim3(BND_THREADS), 0, s2, g, u, flags, partC, partX);
         else
             hipLaunchKernelGGL((adj_boundary_kernel<T, W, DEG, NB, BND_LDS>), dim3(nt), dim3(BND_THREADS), 0, s2, g,
-                               (const cx<T>*)d.vbuf, partC, partX);
+                               u, flags, partC, partX);
         GS_HIP_TRY(hipGetLastError());
     }
     {
         ProfScope _p(K_SPREAD2D, s);
         hipLaunchKernelGGL((adj_interior_kernel<T, W, DEG, NB>), dim3(nt), dim3(IntShape<W>::THREADS), 0, s, g,
-                           (const cx<T>*)d.vbuf, partI, partR);
+                           u, flags, partI, partR);
         GS_HIP_TRY(hipGetLastError());
     }
     if (s2 != s) {

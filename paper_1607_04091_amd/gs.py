@@ -70,7 +70,8 @@ class SolveInfo(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("J", ctypes.c_int), ("p", ctypes.c_int), ("N", ctypes.c_int),
                 ("precision", ctypes.c_int), ("M", ctypes.c_int64), ("grid_n", ctypes.c_int),
-                ("window_w32", ctypes.c_int), ("window_w64", ctypes.c_int), ("device_bytes", ctypes.c_int64)]
+                ("window_w32", ctypes.c_int), ("window_w64", ctypes.c_int), ("device_bytes", ctypes.c_int64),
+                ("exact_nodes", ctypes.c_int)]
 
 
 def _load():

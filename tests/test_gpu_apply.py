@@ -249,3 +249,47 @@ def test_full_weight_adjoint(gs, dim, prec):
                                  gs.GS_WEIGHT_FULL | (gs.GS_APPLY_F64 if f64 else 0), None)
     assert rc == gs.GS_ERR_INVALID_ARG
     plan.destroy()
+
+
+@pytest.mark.parametrize("dim,J,p,eps,n_per_dim", [(1, 8, 2, 0.5, 1024), (1, 7, 4, 0.25, 700), (1, 6, 3, 1.0, 200),
+                                                   (2, 5, 4, 0.5, 64), (2, 4, 2, 0.25, 40), (2, 6, 1, 1.0, 64)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_uniform_nodes_exact_path(gs, dim, J, p, eps, n_per_dim, prec):
+    """Frequencies on a grid eps Z (eps = 1, 1/2, 1/4; the paper's uniform
+    case, Sec. 3.2): the plan takes the exact path (a zero-padded FFT read at
+    the nodes, no window).  Against the dense oracle the FP64 error is then at
+    the FFT's rounding level, well below the windowed NFFT's 8e-14; FP32 as
+    usual.  The 1D C1 shape (db2, J = 8, 1024 points k/2) is the first case; the
+    2D cases are full uniform grids (the paper's Uniform 2D pattern, smaller)."""
+    say(f"[uniform] dim={dim} J={J} p={p} eps={eps} prec={prec}")
+    N = 1 << J
+    k = np.arange(n_per_dim) - n_per_dim // 2
+    if dim == 1:
+        xi = eps * k.astype(float)
+        T = basis.dense_T_1d(xi, J, p)
+        shape = (N,)
+    else:
+        KX, KY = np.meshgrid(k, k, indexing="ij")
+        xi = eps * np.stack([KX.ravel(), KY.ravel()], axis=1).astype(float)
+        T = basis.dense_T_2d(xi, J, p)
+        shape = (N, N)
+    M = xi.shape[0]
+    rng = np.random.default_rng(90 + J)
+    mu = rng.uniform(0.5, 1.5, M)
+    plan = gs.gs_plan(dim, J, p, xi, mu, precision=prec)
+    assert plan.info()["exact_nodes"] == 1
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    x = crandn(rng, shape)
+    u = crandn(rng, M)
+    tol = 1e-14 if prec == 0 else 2e-5
+    s = np.sqrt(mu)
+    assert_close(to_host(plan.apply_T(to_dev(x, dt), weighted=True)), s * (T @ x.reshape(-1)), tol, "W^1/2 T x")
+    assert_close(to_host(plan.apply_TH(to_dev(u, dt), weighted=True)).reshape(-1), T.conj().T @ (s * u), tol,
+                 "T^H W^1/2 u")
+    plan.destroy()
+    # one point off the grid: the windowed NFFT path
+    xi2 = xi.copy()
+    xi2[0] = xi2[0] + 1e-3
+    plan2 = gs.gs_plan(dim, J, p, xi2, mu, precision=prec)
+    assert plan2.info()["exact_nodes"] == 0
+    plan2.destroy()
