@@ -70,7 +70,9 @@ typedef struct gs_plan gs_plan_t;
 
 /*
  * gs_plan -- build the matrix-free representation of T (the paper's
- * Freq2Wave, Sec. 6.2; its "init").
+ * Freq2Wave, Sec. 6.2; its "init").  The per-point tables (wrapped nodes,
+ * the cell sort, D, L and R of App. A / A.1) are computed on the device; only
+ * the filters (taps, boundary recursion matrices) are constructed on the host.
  *   out        receives the handle (freed with gs_destroy).
  *   dim        1 or 2.
  *   J          scale, N = 2^J coefficients per dimension; 2^J >= 2p and
@@ -221,6 +223,14 @@ int gs_get_plan_info(const gs_plan_t* plan, gs_plan_info* info);
 /* Copies the plan's point permutation (internal order -> caller index) to a
  * HOST buffer of M int32. */
 int gs_get_permutation(const gs_plan_t* plan, int32_t* perm_host);
+
+/* Copies the plan's per-point basis table of one dimension (0 = x, 1 = y) to
+ * a HOST buffer, in the plan's internal point order (see gs_get_permutation):
+ * (2nb+1) x M complex, channel-major, channels [L_0..L_{nb-1}, D,
+ * R_0..R_{nb-1}] as in gs_eval_basis_1d (nb = 0 for Haar, else p); complex128
+ * with f64 != 0, else complex64.  GS_ERR_PRECISION if the plan does not hold
+ * that precision.  (The tables are built on the device by gs_plan.) */
+int gs_get_channels(const gs_plan_t* plan, int dimension, int f64, void* host_out);
 
 const char* gs_strerror(int code);
 int gs_version(void);

@@ -18,6 +18,7 @@
 
 namespace gs {
 size_t adjoint_part_elems(int dim, int64_t M, int nb, int ng);
+hipError_t device_point_tables(Plan& P, const double* xi_host, const double* mu_host, hipStream_t s);
 }
 
 namespace {
@@ -70,13 +71,6 @@ void free_plan(gs::Plan& P) {
     P.side = nullptr;
 }
 
-struct HostPoints {
-    std::vector<uint64_t> pos;             // [dim][M]
-    std::vector<gs::cd> ch;                // [dim][M][nch]
-    std::vector<int32_t> perm;             // internal -> caller
-    std::vector<int32_t> cell_start;       // ncells + 1
-};
-
 int hw_threads() {
     unsigned n = std::thread::hardware_concurrency();
     return n == 0 ? 4 : (int)std::min(n, 64u);
@@ -94,47 +88,15 @@ int uniform_level(const double* v, int64_t n) {
     return a;
 }
 
-uint64_t fixed_point_frac(double xi, int J) {
-    const double eta = std::ldexp(xi, -J);
-    const double f = eta - std::floor(eta);   // exact, in [0, 1)
-    long double r = std::nearbyint(std::ldexp((long double)f, 64));
-    if (r >= std::ldexp((long double)1, 64)) r = 0;   // wraps to 0 on the torus
-    return (uint64_t)r;
-}
 
 template <class T>
-hipError_t upload_prec(gs::Plan& P, const HostPoints& H, const std::vector<double>& smu_sorted, int w, int deg,
-                       double beta, hipStream_t s) {
+hipError_t upload_prec(gs::Plan& P, int w, int deg, double beta) {
     using namespace gs;
     PrecData<T>& d = prec<T>(P);
-    const size_t M = P.M, nch = 2 * P.nb + 1;
+    const size_t M = P.M;
     d.present = true;
     d.w = w;
     d.deg = deg;
-    // positions
-    GS_HIP_TRY(dalloc(P, d.pos, (size_t)P.dim * M));
-    {
-        std::vector<P_t<T>> hp((size_t)P.dim * M);
-        for (size_t i = 0; i < hp.size(); ++i) hp[i] = (P_t<T>)(H.pos[i] >> (64 - posw<T>::bits));
-        GS_HIP_TRY(hipMemcpy(d.pos, hp.data(), hp.size() * sizeof(P_t<T>), hipMemcpyHostToDevice));
-    }
-    // channels (SoA: [nch][M] per dimension), internal order
-    for (int dm = 0; dm < P.dim; ++dm) {
-        cx<T>*& dst = dm == 0 ? d.chx : d.chy;
-        GS_HIP_TRY(dalloc(P, dst, nch * M));
-        std::vector<cx<T>> hc(nch * M);
-        for (size_t q = 0; q < M; ++q) {
-            const cd* src = &H.ch[((size_t)dm * M + q) * nch];
-            for (size_t c = 0; c < nch; ++c) hc[c * M + q] = mk<T>((T)src[c].real(), (T)src[c].imag());
-        }
-        GS_HIP_TRY(hipMemcpy(dst, hc.data(), hc.size() * sizeof(cx<T>), hipMemcpyHostToDevice));
-    }
-    {
-        GS_HIP_TRY(dalloc(P, d.smu, M));
-        std::vector<T> hs(M);
-        for (size_t q = 0; q < M; ++q) hs[q] = (T)smu_sorted[q];
-        GS_HIP_TRY(hipMemcpy(d.smu, hs.data(), M * sizeof(T), hipMemcpyHostToDevice));
-    }
     // window and deapodization.  On exact nodes (P.exact) the window is the
     // linear hat, which at a node has the taps (.., 0, 1, 0, ..): interpolation
     // and spreading then read and write the node itself, with no window error,
@@ -180,7 +142,6 @@ hipError_t upload_prec(gs::Plan& P, const HostPoints& H, const std::vector<doubl
     GS_HIP_TRY(dalloc(P, d.part, d.part_elems));
     GS_HIP_TRY(dalloc(P, d.vbuf, M));
     GS_HIP_TRY(dalloc(P, d.ybuf, M));
-    (void)s;
     return hipSuccess;
 }
 
@@ -308,88 +269,25 @@ int gs_plan(gs_plan_t** out, int dim, int J, int p, int64_t M, const double* xi,
     }
     hipStream_t s = (hipStream_t)stream;
 
-    // ---- host math (FP64 / extended)
-    const int nch = 2 * P.nb + 1;
-    HostPoints H;
-    std::vector<gs::cd> ch;
     try {
-        (void)gs::basis_data(p);
-        std::vector<gs::cd> tmp((size_t)M * nch);
-        ch.resize((size_t)dim * M * nch);
-        for (int dm = 0; dm < dim; ++dm) {
-            gs::eval_basis_1d(J, p, M, xi + dm, dim, tmp.data(), hw_threads());
-            std::copy(tmp.begin(), tmp.end(), ch.begin() + (size_t)dm * M * nch);
-        }
+        (void)gs::basis_data(p);   // filters of this p (host construction, cached)
     } catch (const std::bad_alloc&) {
         return GS_ERR_NOMEM;
     } catch (...) {
         return GS_ERR_UNSUPPORTED;
     }
-    // positions and cell keys
-    std::vector<uint64_t> pos((size_t)dim * M);
-    std::vector<int32_t> key(M);
-    for (int64_t m = 0; m < M; ++m) {
-        int64_t cell[2] = {0, 0};
-        for (int dm = 0; dm < dim; ++dm) {
-            const uint64_t u = fixed_point_frac(xi[m * dim + dm], J);
-            pos[(size_t)dm * M + m] = u;
-            cell[dm] = (int64_t)(u >> (64 - P.G));
-        }
-        key[m] = (int32_t)(dim == 2 ? gs::tile_key(cell[0], cell[1], P.ts, P.ng) : cell[0]);
-    }
-    // counting sort by cell (stable)
-    const int64_t ncells = dim == 2 ? (int64_t)P.ng * P.ng : P.ng;
-    H.cell_start.assign(ncells + 1, 0);
-    for (int64_t m = 0; m < M; ++m) H.cell_start[key[m] + 1]++;
-    for (int64_t c = 0; c < ncells; ++c) H.cell_start[c + 1] += H.cell_start[c];
-    // 2D tiles in decreasing point count: the tile kernels take the heaviest tiles first
-    std::vector<int32_t> tile_order;
-    if (dim == 2 && P.ts == gs::TILE) {
-        const int64_t nt = (int64_t)(P.ng / P.ts) * (P.ng / P.ts), tc = (int64_t)P.ts * P.ts;
-        tile_order.resize(nt);
-        for (int64_t t = 0; t < nt; ++t) tile_order[t] = (int32_t)t;
-        std::stable_sort(tile_order.begin(), tile_order.end(), [&](int32_t a, int32_t b) {
-            return H.cell_start[(a + 1) * tc] - H.cell_start[a * tc] > H.cell_start[(b + 1) * tc] - H.cell_start[b * tc];
-        });
-    }
-    H.perm.resize(M);
-    {
-        std::vector<int32_t> fill(H.cell_start.begin(), H.cell_start.end() - 1);
-        for (int64_t m = 0; m < M; ++m) H.perm[fill[key[m]]++] = (int32_t)m;
-    }
-    H.pos.resize((size_t)dim * M);
-    H.ch.resize((size_t)dim * M * nch);
-    std::vector<double> smu(M);
-    for (int64_t q = 0; q < M; ++q) {
-        const int64_t m = H.perm[q];
-        for (int dm = 0; dm < dim; ++dm) {
-            H.pos[(size_t)dm * M + q] = pos[(size_t)dm * M + m];
-            std::copy_n(&ch[((size_t)dm * M + m) * nch], nch, &H.ch[((size_t)dm * M + q) * nch]);
-        }
-        smu[q] = mu ? std::sqrt(mu[m]) : 1.0;
-    }
 
-    // ---- device
+    // ---- device: point tables on the device, then the window, twiddle and workspace tables
+    P.d64.present = precision == GS_F64 || precision == GS_F32_MIXED;
+    P.d32.present = precision == GS_F32 || precision == GS_F32_MIXED;
     hipError_t e = hipSuccess;
     do {
-        if ((e = dalloc(P, P.perm, (size_t)M)) != hipSuccess) break;
-        if ((e = hipMemcpy(P.perm, H.perm.data(), M * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess) break;
-        if ((e = dalloc(P, P.cell_start, (size_t)ncells + 1)) != hipSuccess) break;
-        if ((e = hipMemcpy(P.cell_start, H.cell_start.data(), (ncells + 1) * sizeof(int32_t),
-                           hipMemcpyHostToDevice)) != hipSuccess)
-            break;
-        if (!tile_order.empty()) {
-            if ((e = dalloc(P, P.tile_order, tile_order.size())) != hipSuccess) break;
-            if ((e = hipMemcpy(P.tile_order, tile_order.data(), tile_order.size() * sizeof(int32_t),
-                               hipMemcpyHostToDevice)) != hipSuccess)
-                break;
-        }
-        if (precision == GS_F64 || precision == GS_F32_MIXED)
-            if ((e = upload_prec<double>(P, H, smu, gs::W64, gs::DEG64, 2.35 * gs::W64, s)) != hipSuccess) break;
-        if (precision == GS_F32 || precision == GS_F32_MIXED)
-            if ((e = upload_prec<float>(P, H, smu, gs::W32, gs::DEG32, 2.35 * gs::W32, s)) != hipSuccess) break;
         if ((e = gs::solver_alloc(P)) != hipSuccess) break;
-        if ((e = hipMemcpy(P.smu64, smu.data(), M * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) break;
+        if ((e = gs::device_point_tables(P, xi, mu, s)) != hipSuccess) break;
+        if (P.d64.present)
+            if ((e = upload_prec<double>(P, gs::W64, gs::DEG64, 2.35 * gs::W64)) != hipSuccess) break;
+        if (P.d32.present)
+            if ((e = upload_prec<float>(P, gs::W32, gs::DEG32, 2.35 * gs::W32)) != hipSuccess) break;
         if (dim == 2 && P.nb > 0) {
             if ((e = hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking)) != hipSuccess) break;
             if ((e = hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming)) != hipSuccess) break;
@@ -539,6 +437,24 @@ int gs_get_plan_info(const gs_plan_t* plan, gs_plan_info* info) {
     info->device_bytes = P.bytes;
     info->exact_nodes = P.exact ? 1 : 0;
     return GS_OK;
+}
+
+int gs_get_channels(const gs_plan_t* plan, int dimension, int f64, void* host_out) {
+    if (!plan || !host_out) return GS_ERR_INVALID_ARG;
+    const gs::Plan& P = plan->impl;
+    if (dimension < 0 || dimension >= P.dim) return GS_ERR_INVALID_ARG;
+    const size_t n = (size_t)(2 * P.nb + 1) * P.M;
+    hipError_t e;
+    if (f64) {
+        if (!P.d64.present) return GS_ERR_PRECISION;
+        e = hipMemcpy(host_out, dimension == 0 ? P.d64.chx : P.d64.chy, n * sizeof(gs::cx<double>),
+                      hipMemcpyDeviceToHost);
+    } else {
+        if (!P.d32.present) return GS_ERR_PRECISION;
+        e = hipMemcpy(host_out, dimension == 0 ? P.d32.chx : P.d32.chy, n * sizeof(gs::cx<float>),
+                      hipMemcpyDeviceToHost);
+    }
+    return e == hipSuccess ? GS_OK : hip_fail(e);
 }
 
 int gs_get_permutation(const gs_plan_t* plan, int32_t* perm_host) {

@@ -39,7 +39,7 @@ def _wflags(weighted):
 
 EXPORTS = [
     "gs_plan", "gs_apply_T", "gs_apply_TH", "gs_apply_TH_noalloc", "gs_solve", "gs_solve_batch", "gs_destroy", "gs_get_plan_info",
-    "gs_get_permutation", "gs_strerror", "gs_version", "gs_filter_taps", "gs_boundary_filters",
+    "gs_get_permutation", "gs_get_channels", "gs_strerror", "gs_version", "gs_filter_taps", "gs_boundary_filters",
     "gs_eval_basis_1d", "gs_profile_enable", "gs_profile_read",
     "gs_cnn_param_count", "gs_cnn_create", "gs_cnn_destroy", "gs_cnn_set_weights", "gs_cnn_get_weights",
     "gs_cnn_get_grads", "gs_cnn_get_state", "gs_cnn_set_state", "gs_cnn_forward", "gs_cnn_backward", "gs_cnn_step",
@@ -109,6 +109,7 @@ def _load():
     lib.gs_destroy.restype = None
     lib.gs_get_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     lib.gs_get_permutation.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.gs_get_channels.argtypes = [vp, i32, i32, vp]
     lib.gs_strerror.argtypes = [i32]
     lib.gs_strerror.restype = ctypes.c_char_p
     lib.gs_version.argtypes = []
@@ -270,6 +271,16 @@ class Plan:
         rc = _lib.gs_get_permutation(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         if rc:
             raise GSError(rc, "gs_get_permutation")
+        return out
+
+    def channels(self, dimension=0, f64=True) -> np.ndarray:
+        """The per-point basis table of one dimension, (2nb+1, M) complex, in
+        the plan's internal point order."""
+        nch = 2 * (0 if self.p == 1 else self.p) + 1
+        out = np.zeros((nch, self.M), dtype=np.complex128 if f64 else np.complex64)
+        rc = _lib.gs_get_channels(self.handle, int(dimension), int(bool(f64)), out.ctypes.data_as(ctypes.c_void_p))
+        if rc:
+            raise GSError(rc, "gs_get_channels")
         return out
 
     def coef_shape(self):

@@ -293,3 +293,39 @@ def test_uniform_nodes_exact_path(gs, dim, J, p, eps, n_per_dim, prec):
     plan2 = gs.gs_plan(dim, J, p, xi2, mu, precision=prec)
     assert plan2.info()["exact_nodes"] == 0
     plan2.destroy()
+
+
+@pytest.mark.parametrize("dim,J,p,M", [(2, 9, 4, 200_000), (1, 14, 4, 65_536), (2, 6, 8, 3000), (1, 20, 3, 5000),
+                                       (2, 5, 1, 2000), (1, 4, 2, 300)])
+def test_device_plan_tables(gs, dim, J, p, M):
+    """The plan's per-point tables are built on the device: they must equal
+    the host evaluation (gs_eval_basis_1d, App. A product and App. A.1
+    recursion) to 1e-14 in FP64, the FP32 tables must be the FP64 ones rounded,
+    and the permutation must be the stable sort by cell (tile-major in 2D)."""
+    say(f"[device plan] dim={dim} J={J} p={p} M={M}")
+    rng = np.random.default_rng(500 + J + p)
+    N = 1 << J
+    xi = rng.uniform(-1.2 * N, 1.2 * N, (M, 2) if dim == 2 else M)
+    xi[:3] = xi[3]                                  # repeated points keep their input order
+    plan = gs.gs_plan(dim, J, p, xi, rng.uniform(0.5, 2, M), precision=gs.GS_F32_MIXED if J <= 14 else gs.GS_F64)
+    perm = plan.permutation()
+    assert np.array_equal(np.sort(perm), np.arange(M))
+    # stable sort by cell: the key of the wrapped node, points of a cell in input order
+    ng = max(2 * N, 16)
+    cells = np.floor((np.asarray(xi).reshape(M, dim) / N % 1.0) * ng).astype(np.int64) % ng
+    if dim == 2:
+        ts = min(32, ng)
+        ntx = ng // ts
+        key = ((cells[:, 0] // ts) * ntx + cells[:, 1] // ts) * ts * ts + (cells[:, 0] % ts) * ts + cells[:, 1] % ts
+    else:
+        key = cells[:, 0]
+    assert np.array_equal(perm, np.argsort(key, kind="stable"))
+    for d in range(dim):
+        x = np.asarray(xi).reshape(M, dim)[perm, d]
+        host = gs.gs_eval_basis_1d(J, p, x).T          # (nch, M)
+        dev64 = plan.channels(d, f64=True)
+        assert np.max(np.abs(dev64 - host)) <= 1e-14 * np.max(np.abs(host)), np.max(np.abs(dev64 - host))
+        if J <= 14:
+            dev32 = plan.channels(d, f64=False)
+            assert np.array_equal(dev32, dev64.astype(np.complex64))
+    plan.destroy()
