@@ -204,6 +204,22 @@ int gs_solve(const gs_plan_t* plan, const void* y, void* x, const gs_solve_opts*
 int gs_solve_batch(const gs_plan_t* const* plans, int count, const void* const* y, void* const* x,
                    const gs_solve_opts* opts, gs_solve_info* infos, int n_streams, void* stream);
 
+/*
+ * gs_weval -- evaluate a representation in V_J^int on a dyadic grid (the
+ * paper's weval, Sec. 6.2; the image-space output of Figs. 1-2):
+ *   1D: out[j] = sum_n coef[n] s_n(x_j), x_j = -1/2 + j 2^-R, j = 0..2^R;
+ *   2D: out[a (2^R+1) + b] = sum_{i,j} coef[i N + j] s_i(x_a) s_j(x_b).
+ * s_n is basis function n of Sec. 3.3 in space (the column order of gs_plan:
+ * left boundary functions, interior translates, right boundary functions),
+ * evaluated by the cascade algorithm: phi at the integers from the
+ * refinement equation, then doubling the resolution to R - J; the boundary
+ * functions are their defining combinations of restricted translates
+ * (App. A.1).  coef and out: device complex128 (N^dim and (2^R+1)^dim).
+ * R >= J, R - J <= 20, R <= 26 (1D) or 13 (2D).  Allocates temporary device
+ * memory and returns after the result is complete (synchronizes `stream`).
+ */
+int gs_weval(int dim, int J, int p, int R, const void* coef, void* out, void* stream);
+
 /* Releases every resource of the plan (NULL is ignored). */
 void gs_destroy(gs_plan_t* plan);
 

@@ -80,3 +80,46 @@ def trapezoid_inner(x, f, g):
     wts = np.full(x.size, hstep)
     wts[0] = wts[-1] = hstep / 2
     return float(np.sum(wts * f * g))
+
+
+def basis_on_grid(J: int, p: int, R: int):
+    """(x, S) with x_j = -1/2 + j / 2^R (j = 0..2^R) and S[n, j] = s_n(x_j), the
+    basis of V_J^int on [-1/2, 1/2] (Sec. 3.3) in space, R >= J:
+      n <  p      : 2^{J/2} phi^L_n(2^J (x + 1/2))
+      p <= n < N-p: 2^{J/2} phi(2^J (x + 1/2) - n)
+      n >= N-p    : 2^{J/2} phi^R_{N-1-n}(2^J (x - 1/2))
+    The boundary functions are the restricted combinations of translates that
+    define them (App. A.1): phi^L_k(t) = sum_i a_{k,i} phi(t - n_i) for t >= 0,
+    and phi^R_k(t) = phi^{bL}_k(-t) for t <= 0, where the reflected filter
+    h_{1-k} has the scaling function phi(1 - t).  phi comes from the cascade at
+    resolution r = R - J, so every needed value is read at a grid point."""
+    from . import cdv
+    if R < J:
+        raise ValueError("need R >= J")
+    r = R - J
+    N = 1 << J
+    xg, ph = phi_on_grid(p, r)
+    t = np.arange(2 ** R + 1) / 2 ** r                # t = 2^J (x + 1/2) in [0, N]
+    S = np.zeros((N, t.size))
+    nb = 0 if p == 1 else p
+    for n in range(nb, N - nb):
+        S[n] = eval_translates(xg, ph, r, t, n)
+    if nb:
+        eL, eR = cdv.left_edge(p), cdv.flipped_edge(p)
+        A, B = eL.coef_fp64(), eR.coef_fp64()
+        u = t - N                                       # <= 0 on the whole interval
+        for k in range(p):
+            S[k] = sum(A[k, i] * eval_translates(xg, ph, r, t, n) for i, n in enumerate(eL.trans))
+            S[N - 1 - k] = sum(B[k, i] * eval_translates(xg, ph, r, 1 + u + n, 0) for i, n in enumerate(eR.trans))
+    return t / N - 0.5, 2.0 ** (J / 2) * S
+
+
+def weval(coefs, J: int, p: int, R: int):
+    """f = sum_n x_n s_n on the dyadic grid x_j = -1/2 + j / 2^R (1D), or
+    f(x_a, y_b) = sum_{i,j} X[i, j] s_i(x_a) s_j(y_b) (2D, X row-major with i
+    the x index): the weval of Sec. 6.2."""
+    c = np.asarray(coefs)
+    x, S = basis_on_grid(J, p, R)
+    if c.ndim == 1:
+        return x, c @ S
+    return x, S.T @ c @ S

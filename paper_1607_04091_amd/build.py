@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libgs.so")
 
-HIP_SOURCES = ["api.hip", "plan.hip", "nfft.hip", "nfft2d.hip", "cgls.hip", "cnn.hip"]
+HIP_SOURCES = ["api.hip", "plan.hip", "nfft.hip", "nfft2d.hip", "cgls.hip", "cnn.hip", "weval.hip"]
 CXX_SOURCES = ["host_math.cpp"]
 ARCH = os.environ.get("GS_OFFLOAD_ARCH", "gfx950")
 

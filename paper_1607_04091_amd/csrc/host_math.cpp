@@ -253,7 +253,29 @@ BoundaryEdge edge_construction(const std::vector<ld>& hk, int p) {
     for (int i = 0; i < p * (2 * p - 1); ++i) e.V[i] = (double)Vld[i];
     e.v0.resize(p);
     for (int k = 0; k < p; ++k) e.v0[k] = (double)bv[k];
+    e.coef.resize(nt * p);
+    for (int i = 0; i < nt * p; ++i) e.coef[i] = (double)Cf[i];
     return e;
+}
+
+// phi at the integers n = -p+1..p: the fixed point of the refinement equation
+// phi(n) = 2 sum_k h_k phi(2n - k) restricted to the integers, normalized by
+// the partition of unity sum_n phi(n) = 1.  Haar: phi = 1 on [0, 1).
+std::vector<ld> phi_at_integers(const std::vector<ld>& hk, int p) {
+    if (p == 1) return {1.0L, 0.0L};
+    const int n = 2 * p;   // integers -p+1..p
+    std::vector<ld> A(n * n, 0), b(n, 0);
+    for (int a = 0; a < n; ++a)
+        for (int c = 0; c < n; ++c) {
+            const int k = 2 * (a - p + 1) - (c - p + 1);
+            if (k >= -p + 1 && k <= p) A[a * n + c] = 2 * hk[k + p - 1];
+            if (a == c) A[a * n + c] -= 1;
+        }
+    // the system (A - I) v = 0 has rank n - 1: replace its last row by the normalization
+    for (int c = 0; c < n; ++c) A[(n - 1) * n + c] = 1;
+    b[n - 1] = 1;
+    solve_dense(A, b, n);
+    return b;
 }
 
 }  // namespace
@@ -269,6 +291,10 @@ const BasisData& basis_data(int p) {
     d.p = p;
     const std::vector<ld> hk = daubechies_taps(p);
     d.taps.assign(hk.begin(), hk.end());
+    {
+        const std::vector<ld> pv = phi_at_integers(hk, p);
+        d.phi_int.assign(pv.begin(), pv.end());
+    }
     if (p > 1) {
         d.left = edge_construction(hk, p);
         std::vector<ld> flip(2 * p);

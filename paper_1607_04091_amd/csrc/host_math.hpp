@@ -15,12 +15,15 @@ struct BoundaryEdge {
     std::vector<double> U;   // p x p row-major      (H / sqrt 2)
     std::vector<double> V;   // p x (2p-1) row-major (h / sqrt 2), columns m = p..3p-2
     std::vector<double> v0;  // v1(0)
+    std::vector<double> coef;  // (2p-1) x p row-major: coefficient of the restricted
+                               // translate phi(. - n), n = -p+1..p-1 (row), in phi^L_k (column)
 };
 
 struct BasisData {
     int p = 0;
     std::vector<double> taps;  // h_k, k = -p+1..p
     BoundaryEdge left, right;  // empty for p = 1
+    std::vector<double> phi_int;  // phi at the integers -p+1..p (refinement eigenvector, sum 1)
 };
 
 // Cached per p (thread-safe).  Throws std::runtime_error if p unsupported.

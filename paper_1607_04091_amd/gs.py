@@ -39,7 +39,7 @@ def _wflags(weighted):
 
 EXPORTS = [
     "gs_plan", "gs_apply_T", "gs_apply_TH", "gs_apply_TH_noalloc", "gs_solve", "gs_solve_batch", "gs_destroy", "gs_get_plan_info",
-    "gs_get_permutation", "gs_get_channels", "gs_strerror", "gs_version", "gs_filter_taps", "gs_boundary_filters",
+    "gs_get_permutation", "gs_get_channels", "gs_weval", "gs_strerror", "gs_version", "gs_filter_taps", "gs_boundary_filters",
     "gs_eval_basis_1d", "gs_profile_enable", "gs_profile_read",
     "gs_cnn_param_count", "gs_cnn_create", "gs_cnn_destroy", "gs_cnn_set_weights", "gs_cnn_get_weights",
     "gs_cnn_get_grads", "gs_cnn_get_state", "gs_cnn_set_state", "gs_cnn_forward", "gs_cnn_backward", "gs_cnn_step",
@@ -110,6 +110,7 @@ def _load():
     lib.gs_get_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     lib.gs_get_permutation.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.gs_get_channels.argtypes = [vp, i32, i32, vp]
+    lib.gs_weval.argtypes = [i32, i32, i32, i32, vp, vp, vp]
     lib.gs_strerror.argtypes = [i32]
     lib.gs_strerror.restype = ctypes.c_char_p
     lib.gs_version.argtypes = []
@@ -229,6 +230,29 @@ def gs_eval_basis_1d(J: int, p: int, xi) -> np.ndarray:
     if rc:
         raise GSError(rc, "gs_eval_basis_1d")
     return out
+
+
+# ------------------------------------------------------------------ evaluation in space
+
+def gs_weval(coef, J: int, p: int, R: int, out=None, stream=None):
+    """f on the dyadic grid x_j = -1/2 + j 2^-R (j = 0..2^R) from the
+    coefficients (a complex128 GPU tensor of shape (N,) or (N, N)); returns
+    (x as a numpy array, f as a complex128 GPU tensor of shape (2^R+1,)^dim)."""
+    import torch
+    dim = coef.dim()
+    N = 1 << J
+    if dim not in (1, 2):
+        raise ValueError("coef must be 1D or 2D")
+    _check_vec(coef, torch.complex128, N ** dim, "coef")
+    side = (1 << R) + 1
+    if out is None:
+        out = torch.empty((side,) * dim, dtype=torch.complex128, device=coef.device)
+    _check_vec(out, torch.complex128, side ** dim, "out", like=coef)
+    rc = _lib.gs_weval(dim, J, p, R, ctypes.c_void_p(coef.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                       _stream(stream))
+    if rc:
+        raise GSError(rc, "gs_weval")
+    return np.arange(side) / (1 << R) - 0.5, out
 
 
 # ------------------------------------------------------------------ plans
