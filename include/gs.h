@@ -162,6 +162,9 @@ typedef struct gs_solve_info {
     double rel_residual;        /* final relative normal residual (recurred)           */
     double rel_residual_fp64;   /* recomputed with FP64 applies (mixed form), else -1  */
     int    warm_start_used;     /* 1 if the iteration started from the caller's x0     */
+    int    batch_class;         /* gs_solve_batch: the geometry class whose kernels ran
+                                   this problem batched, or -1 (plain launches)          */
+    int    batch_streams;       /* gs_solve_batch: streams the classes were spread over  */
 } gs_solve_info;
 
 /*
@@ -189,17 +192,22 @@ int gs_solve(const gs_plan_t* plan, const void* y, void* x, const gs_solve_opts*
  * vectors).  One options struct serves every problem; opts->history must be
  * NULL.  infos: HOST array of `count` results.
  *
- * Each problem's CGLS iteration is captured once as a HIP graph; the graphs
- * of the problems still running are launched round after round on up to
- * n_streams internal streams (problems placed heaviest first), and every
- * opts->check_every rounds one host synchronization reads all stop flags and
- * retires the problems that are done.  n_streams = 0 picks the stream count
- * (1, 2, 4, 8, capped at count) from short timed trial rounds; otherwise
- * 1..64.  The iterates are those gs_solve produces (same kernels, same
- * order), so per problem the result equals gs_solve's bit for bit.  The
- * internal streams wait for `stream` on entry; the call returns after all
- * work is done.  Returns GS_OK when every problem converged, GS_NOT_CONVERGED
- * when some did not (see infos[i].status), or the first error.
+ * Problems whose plans share one geometry (2D, grids of at least 32 x 32
+ * cells, same apply precision, N and p) form a class: every kernel of the
+ * class's CGLS iteration runs as ONE launch for all of its active problems,
+ * each problem reading its own arguments; the iterations of a class are
+ * captured as HIP graphs and replayed round after round on one of up to
+ * n_streams internal streams (classes placed heaviest first).  Other plans
+ * run their own captured iterations.  Every opts->check_every rounds one host
+ * synchronization reads all stop flags; finished problems leave their class
+ * (its launches are compacted when a quarter of them have finished).
+ * n_streams = 0 picks the stream count (1, 2, 4, 8, capped at the class
+ * count) from short timed trial rounds; otherwise 1..64.  Per problem the
+ * kernels and their arithmetic are those of gs_solve, so every result equals
+ * gs_solve's bit for bit.  The internal streams wait for `stream` on entry;
+ * the call returns after all work is done.  Returns GS_OK when every problem
+ * converged, GS_NOT_CONVERGED when some did not (see infos[i].status), or the
+ * worst error; every problem is finished and reported either way.
  */
 int gs_solve_batch(const gs_plan_t* const* plans, int count, const void* const* y, void* const* x,
                    const gs_solve_opts* opts, gs_solve_info* infos, int n_streams, void* stream);

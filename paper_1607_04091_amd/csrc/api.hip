@@ -151,6 +151,7 @@ namespace gs {
 hipError_t solver_alloc(Plan& P);
 
 bool g_prof_enabled = false;
+thread_local LaunchCtx* g_launch = nullptr;
 
 namespace {
 struct ProfRec {

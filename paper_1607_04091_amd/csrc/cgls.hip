@@ -51,7 +51,17 @@ __device__ inline double sum_partials(const double* __restrict__ red, double* sh
 }
 
 template <class T>
-__global__ void __launch_bounds__(RT) norm2_partial_kernel(const cx<T>* __restrict__ v, int64_t n, double* __restrict__ red) {
+struct Norm2Args {
+    const cx<T>* v;
+    int64_t n;
+    double* red;
+};
+
+template <class T>
+__device__ __forceinline__ void norm2_partial_kernel_body(const Norm2Args<T>& A) {
+    const cx<T>* __restrict__ v = A.v;
+    const int64_t n = A.n;
+    double* __restrict__ red = A.red;
     __shared__ double sh[RT];
     double acc = 0;
     for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)RB * RT) {
@@ -60,6 +70,16 @@ __global__ void __launch_bounds__(RT) norm2_partial_kernel(const cx<T>* __restri
     }
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) red[blockIdx.x] = s;
+}
+
+template <class T, bool BATCH>
+__global__ void __launch_bounds__(RT) norm2_partial_kernel(Norm2Args<T> one, const Norm2Args<T>* __restrict__ many) {
+    if constexpr (BATCH) {
+        const Norm2Args<T> a = kernel_args<true>(one, many);
+        norm2_partial_kernel_body<T>(a);
+    } else {
+        norm2_partial_kernel_body<T>(one);
+    }
 }
 
 // b = sqrt(mu) * y[perm]; r = b (x0 = 0) ; optional FP32 copy of r
@@ -135,11 +155,29 @@ __global__ void set_ref64_kernel(double* __restrict__ scal, const double* __rest
 
 // x += alpha p ; r -= alpha q ; alpha = gamma / ||q||^2
 template <class T, class Tr>
-__global__ void __launch_bounds__(RT) update_xr_kernel(double* __restrict__ scal, const double* __restrict__ red,
-                                                       cx<double>* __restrict__ x, const cx<double>* __restrict__ p,
-                                                       int64_t nx, cx<double>* __restrict__ r,
-                                                       const cx<T>* __restrict__ q, cx<Tr>* __restrict__ rT,
-                                                       int64_t M) {
+struct UpdateXrArgs {
+    double* scal;
+    const double* red;
+    cx<double>* x;
+    const cx<double>* p;
+    int64_t nx;
+    cx<double>* r;
+    const cx<T>* q;
+    cx<Tr>* rT;
+    int64_t M;
+};
+
+template <class T, class Tr>
+__device__ __forceinline__ void update_xr_kernel_body(const UpdateXrArgs<T, Tr>& A) {
+    double* __restrict__ scal = A.scal;
+    const double* __restrict__ red = A.red;
+    cx<double>* __restrict__ x = A.x;
+    const cx<double>* __restrict__ p = A.p;
+    const int64_t nx = A.nx;
+    cx<double>* __restrict__ r = A.r;
+    const cx<T>* __restrict__ q = A.q;
+    cx<Tr>* __restrict__ rT = A.rT;
+    const int64_t M = A.M;
     __shared__ double sh[RT];
     const double delta = sum_partials(red, sh);
     if (scal[S_DONE] != 0.0) return;
@@ -172,15 +210,42 @@ __global__ void __launch_bounds__(RT) update_xr_kernel(double* __restrict__ scal
     }
 }
 
+template <class T, class Tr, bool BATCH>
+__global__ void __launch_bounds__(RT) update_xr_kernel(UpdateXrArgs<T, Tr> one, const UpdateXrArgs<T, Tr>* __restrict__ many) {
+    if constexpr (BATCH) {
+        const UpdateXrArgs<T, Tr> a = kernel_args<true>(one, many);
+        update_xr_kernel_body<T, Tr>(a);
+    } else {
+        update_xr_kernel_body<T, Tr>(one);
+    }
+}
+
 // p = s + beta p, beta = ||s||^2 / gamma (gamma not yet updated).  With
 // xbest (reduced-precision recurrences), x is also copied there whenever its
 // normal residual ||s||^2 is the smallest of the run, so that a recurrence
 // stopped past its accuracy floor can return its best iterate.
 template <class T, class Tp>
-__global__ void __launch_bounds__(RT) update_p_kernel(const double* __restrict__ scal, const double* __restrict__ red,
-                                                      cx<double>* __restrict__ p, const cx<T>* __restrict__ s,
-                                                      cx<Tp>* __restrict__ pT, int64_t nx,
-                                                      const cx<double>* __restrict__ x, cx<double>* __restrict__ xbest) {
+struct UpdatePArgs {
+    const double* scal;
+    const double* red;
+    cx<double>* p;
+    const cx<T>* s;
+    cx<Tp>* pT;
+    int64_t nx;
+    const cx<double>* x;
+    cx<double>* xbest;
+};
+
+template <class T, class Tp>
+__device__ __forceinline__ void update_p_kernel_body(const UpdatePArgs<T, Tp>& A) {
+    const double* __restrict__ scal = A.scal;
+    const double* __restrict__ red = A.red;
+    cx<double>* __restrict__ p = A.p;
+    const cx<T>* __restrict__ s = A.s;
+    cx<Tp>* __restrict__ pT = A.pT;
+    const int64_t nx = A.nx;
+    const cx<double>* __restrict__ x = A.x;
+    cx<double>* __restrict__ xbest = A.xbest;
     __shared__ double sh[RT];
     const double gnew = sum_partials(red, sh);
     if (scal[S_DONE] != 0.0 || scal[S_BREAK] != 0.0) return;
@@ -197,14 +262,34 @@ __global__ void __launch_bounds__(RT) update_p_kernel(const double* __restrict__
     }
 }
 
+template <class T, class Tp, bool BATCH>
+__global__ void __launch_bounds__(RT) update_p_kernel(UpdatePArgs<T, Tp> one, const UpdatePArgs<T, Tp>* __restrict__ many) {
+    if constexpr (BATCH) {
+        const UpdatePArgs<T, Tp> a = kernel_args<true>(one, many);
+        update_p_kernel_body<T, Tp>(a);
+    } else {
+        update_p_kernel_body<T, Tp>(one);
+    }
+}
+
 __global__ void copy_kernel(const cx<double>* __restrict__ a, cx<double>* __restrict__ o, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) o[i] = a[i];
 }
 
 // gamma = ||s||^2 ; iteration count, history, convergence test
-__global__ void step_scalars_kernel(double* __restrict__ scal, const double* __restrict__ red,
-                                    double* __restrict__ hist, int hist_len) {
+struct StepArgs {
+    double* scal;
+    const double* red;
+    double* hist;
+    int hist_len;
+};
+
+__device__ __forceinline__ void step_scalars_kernel_body(const StepArgs& A) {
+    double* __restrict__ scal = A.scal;
+    const double* __restrict__ red = A.red;
+    double* __restrict__ hist = A.hist;
+    const int hist_len = A.hist_len;
     __shared__ double sh[RT];
     const double gnew = sum_partials(red, sh);
     if (threadIdx.x != 0) return;
@@ -229,11 +314,31 @@ __global__ void step_scalars_kernel(double* __restrict__ scal, const double* __r
     scal[S_GMIN] = fmin(scal[S_GMIN], gnew);
 }
 
+template <bool BATCH>
+__global__ void step_scalars_kernel(StepArgs one, const StepArgs* __restrict__ many) {
+    if constexpr (BATCH) {
+        const StepArgs a = kernel_args<true>(one, many);
+        step_scalars_kernel_body(a);
+    } else {
+        step_scalars_kernel_body(one);
+    }
+}
+
 __global__ void set_scalar_kernel(double* __restrict__ scal, int idx, double v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) scal[idx] = v;
 }
 
 inline int nb256(int64_t n) { return (int)std::max<int64_t>(1, (n + 255) / 256); }
+
+template <class T>
+hipError_t launch_norm2(const cx<T>* v, int64_t n, double* red, hipStream_t st) {
+    using A = Norm2Args<T>;
+    return launch_site(A{v, n, red}, [&](const A& one, const A* many, int count) {
+        if (many) hipLaunchKernelGGL((norm2_partial_kernel<T, true>), dim3(RB, count), dim3(RT), 0, st, one, many);
+        else hipLaunchKernelGGL((norm2_partial_kernel<T, false>), dim3(RB, count), dim3(RT), 0, st, one, many);
+        return hipGetLastError();
+    });
+}
 
 hipError_t solver_alloc(Plan& P) {
     auto alloc = [&](auto*& ptr, size_t n) -> hipError_t {
@@ -308,7 +413,7 @@ hipError_t cgls_start(const Plan& P, const cx<double>* x, hipStream_t st, int se
     const int64_t nx = P.dim == 2 ? (int64_t)P.N * P.N : P.N;
     if (o.xbest()) hipLaunchKernelGGL(copy_kernel, dim3(nb256(nx)), dim3(256), 0, st, x, o.xbest(), nx);
     GS_HIP_TRY(launch_apply_TH<T>(P, o.ra(), o.sa(), AFLAGS, st));
-    hipLaunchKernelGGL((norm2_partial_kernel<T>), dim3(RB), dim3(RT), 0, st, o.sa(), nx, P.red);
+    GS_HIP_TRY(launch_norm2<T>(o.sa(), nx, P.red, st));
     hipLaunchKernelGGL((init_p_kernel<T, T>), dim3(nb256(nx)), dim3(256), 0, st, o.sa(), P.ps, o.pcopy(), nx);
     hipLaunchKernelGGL(start_scalars_kernel, dim3(1), dim3(RT), 0, st, P.scal, P.red, set_ref, hist, hist_len);
     return hipGetLastError();
@@ -320,16 +425,33 @@ hipError_t cgls_iteration(const Plan& P, cx<double>* x, hipStream_t st, double* 
     const int64_t nx = P.dim == 2 ? (int64_t)P.N * P.N : P.N;
     const int64_t M = P.M;
     GS_HIP_TRY(launch_apply_T<T>(P, o.pa(), o.qa(), AFLAGS, st));
-    hipLaunchKernelGGL((norm2_partial_kernel<T>), dim3(RB), dim3(RT), 0, st, o.qa(), M, P.red);
-    hipLaunchKernelGGL((update_xr_kernel<T, T>), dim3(1024), dim3(RT), 0, st, P.scal, P.red, x, P.ps, nx, P.r,
-                       o.qa(), o.rcopy(), M);
-    GS_HIP_TRY(hipGetLastError());
+    GS_HIP_TRY(launch_norm2<T>(o.qa(), M, P.red, st));
+    using AX = UpdateXrArgs<T, T>;
+    GS_HIP_TRY(launch_site(AX{P.scal, P.red, x, P.ps, nx, P.r, o.qa(), o.rcopy(), M},
+                           [&](const AX& one, const AX* many, int count) {
+                               if (many) hipLaunchKernelGGL((update_xr_kernel<T, T, true>), dim3(1024, count), dim3(RT), 0, st, one,
+                                                  many);
+        else hipLaunchKernelGGL((update_xr_kernel<T, T, false>), dim3(1024, count), dim3(RT), 0, st, one,
+                                                  many);
+                               return hipGetLastError();
+                           }));
     GS_HIP_TRY(launch_apply_TH<T>(P, o.ra(), o.sa(), AFLAGS, st));
-    hipLaunchKernelGGL((norm2_partial_kernel<T>), dim3(RB), dim3(RT), 0, st, o.sa(), nx, P.red);
-    hipLaunchKernelGGL((update_p_kernel<T, T>), dim3(256), dim3(RT), 0, st, P.scal, P.red, P.ps, o.sa(), o.pcopy(),
-                       nx, (const cx<double>*)x, o.xbest());
-    hipLaunchKernelGGL(step_scalars_kernel, dim3(1), dim3(RT), 0, st, P.scal, P.red, hist, hist_len);
-    return hipGetLastError();
+    GS_HIP_TRY(launch_norm2<T>(o.sa(), nx, P.red, st));
+    using AP = UpdatePArgs<T, T>;
+    GS_HIP_TRY(launch_site(AP{P.scal, P.red, P.ps, o.sa(), o.pcopy(), nx, (const cx<double>*)x, o.xbest()},
+                           [&](const AP& one, const AP* many, int count) {
+                               if (many) hipLaunchKernelGGL((update_p_kernel<T, T, true>), dim3(256, count), dim3(RT), 0, st, one,
+                                                  many);
+        else hipLaunchKernelGGL((update_p_kernel<T, T, false>), dim3(256, count), dim3(RT), 0, st, one,
+                                                  many);
+                               return hipGetLastError();
+                           }));
+    return launch_site(StepArgs{P.scal, P.red, hist, hist_len}, [&](const StepArgs& one, const StepArgs* many,
+                                                                     int count) {
+        if (many) hipLaunchKernelGGL(step_scalars_kernel<true>, dim3(1, count), dim3(RT), 0, st, one, many);
+        else hipLaunchKernelGGL(step_scalars_kernel<false>, dim3(1, count), dim3(RT), 0, st, one, many);
+        return hipGetLastError();
+    });
 }
 
 // r = b - A x with applies of type T (x FP64 on device)
@@ -395,7 +517,7 @@ int solve_setup(const Plan& P, const cx<double>* y, cx<double>* x, const gs_solv
     if (!hipok(hipGetLastError())) return GS_ERR_HIP;
     // reference ||A^H b|| (in apply precision T)
     if (!hipok(launch_apply_TH<T>(P, o.ra(), o.sa(), AFLAGS, st))) return GS_ERR_HIP;
-    hipLaunchKernelGGL((norm2_partial_kernel<T>), dim3(RB), dim3(RT), 0, st, o.sa(), nx, P.red);
+    if (!hipok(launch_norm2<T>(o.sa(), nx, P.red, st))) return GS_ERR_HIP;
     hipLaunchKernelGGL(start_scalars_kernel, dim3(1), dim3(RT), 0, st, P.scal, P.red, 1, nullptr, 0);
     bool warm = opt.warm_start != 0;
     if (warm) {
@@ -450,12 +572,12 @@ int solve_finish(const Plan& P, cx<double>* x, const gs_solve_opts& opt, gs_solv
     if (refine) {
         // FP64 reference ||A^H b|| and recomputed FP64 residual
         if (!hipok(launch_apply_TH<double>(P, P.b, P.ss, AFLAGS, st))) return GS_ERR_HIP;
-        hipLaunchKernelGGL((norm2_partial_kernel<double>), dim3(RB), dim3(RT), 0, st, P.ss, nx, P.red);
+        if (!hipok(launch_norm2<double>(P.ss, nx, P.red, st))) return GS_ERR_HIP;
         hipLaunchKernelGGL(set_ref64_kernel, dim3(1), dim3(RT), 0, st, P.scal, P.red);
         for (;;) {
             if (!hipok(compute_residual<double>(P, x, st))) return GS_ERR_HIP;
             if (!hipok(launch_apply_TH<double>(P, P.r, P.ss, AFLAGS, st))) return GS_ERR_HIP;
-            hipLaunchKernelGGL((norm2_partial_kernel<double>), dim3(RB), dim3(RT), 0, st, P.ss, nx, P.red);
+            if (!hipok(launch_norm2<double>(P.ss, nx, P.red, st))) return GS_ERR_HIP;
             std::vector<double> red(RB);
             if (!hipok(hipMemcpyAsync(red.data(), P.red, RB * sizeof(double), hipMemcpyDeviceToHost, st)))
                 return GS_ERR_HIP;
@@ -512,64 +634,177 @@ int solve_impl(const Plan& P, const cx<double>* y, cx<double>* x, const gs_solve
 
 // ------------------------------------------------------------------ batched solve
 //
-// Many independent problems (each with its own plan) advance together.  The
-// CGLS iteration of every problem is captured as HIP graphs (one iteration,
-// and min(check_every, 16) iterations back to back); each round launches the
-// graphs of the problems still running, spread over several streams, and
-// every `check_every` iterations the host reads all stop flags
-// (one synchronization for the whole batch) and drops the problems that are
-// done.  The update kernels also test the device flag, so a round that runs
-// past convergence changes nothing.  Problems go to streams heaviest first
-// (greedy on the point count).  With n_streams = 0 a short trial picks the
-// stream count: each candidate runs a few rounds of the real iteration and the
-// fastest is kept.
+// Many independent problems (each with its own plan) advance together.
+// Problems whose plans share one geometry -- the 2D tile path, the apply
+// precision, N, the grid side and the number of boundary functions -- form a
+// class.  A class runs each kernel of the CGLS iteration as ONE launch for all
+// of its active problems (gridDim.y = problems): the launch code of the
+// iteration runs once per problem in RECORD mode, which collects every launch
+// site's argument struct, and the structs are uploaded as one device array per
+// site (see LaunchCtx).  A round advances every active problem by one
+// iteration; the rounds of a class are captured as HIP graphs (one iteration,
+// and `ipg` iterations back to back) and replayed on the class's stream.
+// Plans outside the tile path (1D, grids narrower than a tile) form classes of
+// one problem with plain launches.  Every `check_every` rounds one host
+// synchronization reads all stop flags.  Problems that are done leave their
+// class: when at most 3/4 of the problems a class's graphs cover are still
+// active, its argument arrays are compacted and its graphs recaptured.  The
+// update kernels test the device stop flag, so the rounds a finished problem
+// still takes part in change nothing.  Per problem, the kernels, their
+// arithmetic and their order are those of gs_solve, so every result equals
+// the lone solve's bit for bit.
+//
+// Tuner (n_streams = 0): the number of streams the classes are spread over
+// (1, 2, 4 or 8; classes placed heaviest first) is picked from short timed
+// trial rounds of the real iteration, which count as iterations.  Tile side
+// and stage size are not tuned: they set the summation order inside a tile,
+// and a batched problem must reproduce its lone solve and repeated runs
+// must agree bit for bit.
 
 struct BatchItem {
     const Plan* P;
     cx<double>* x;
     bool fp32;
-    // exec[0]: one CGLS iteration; exec[1]: `ipg` iterations back to back
-    hipGraph_t graph[2] = {nullptr, nullptr};
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
-    int stream = 0;
     bool active = true, done = false, broke = false;
     int warm_used = 0;
+    int cls = -1;
 };
 
-static hipError_t capture_iterations(BatchItem& it, int which, int iters, const gs_solve_opts& opt,
-                                     hipStream_t cs) {
-    const Plan& P = *it.P;
-    double* hist = opt.history ? P.hist : nullptr;
-    const int hist_len = std::min(P.hist_len, opt.history_len);
+struct BatchClass {
+    std::vector<int> members;                      // problem indices, class order
+    std::vector<int> captured;                     // positions in members covered by the graphs
+    bool batched = false;                          // kernel-batched launches
+    bool fp32 = false;
+    int stream = 0;
+    double weight = 0;                             // sum of M + 4 ng^2 over members
+    std::vector<size_t> sizes;                     // per launch site: struct size
+    std::vector<std::vector<unsigned char>> rec;   // per site: the structs of all members
+    std::vector<void*> dev;                        // per site: device array for `captured`
+    hipGraph_t graph[2] = {nullptr, nullptr};      // one iteration; ipg iterations
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+};
+
+static bool batchable(const Plan& P) { return P.dim == 2 && P.ts == TILE; }
+
+template <class T>
+static hipError_t iterate_as(const Plan& P, cx<double>* x, hipStream_t st) {
+    return cgls_iteration<T>(P, x, st, nullptr, 0);
+}
+
+static hipError_t iterate(const BatchItem& it, hipStream_t st) {
+    return it.fp32 ? iterate_as<float>(*it.P, it.x, st) : iterate_as<double>(*it.P, it.x, st);
+}
+
+// every launch site's argument structs of the class, member by member
+static hipError_t record_class(BatchClass& c, const std::vector<BatchItem>& items, hipStream_t st) {
+    c.rec.clear();
+    c.sizes.clear();
+    for (size_t k = 0; k < c.members.size(); ++k) {
+        std::vector<std::vector<unsigned char>> one;
+        LaunchCtx ctx;
+        ctx.mode = LaunchCtx::RECORD;
+        ctx.rec = &one;
+        const bool prof = g_prof_enabled;   // nothing is launched: no timing records
+        g_prof_enabled = false;
+        g_launch = &ctx;
+        const hipError_t e = iterate(items[c.members[k]], st);
+        g_launch = nullptr;
+        g_prof_enabled = prof;
+        GS_HIP_TRY(e);
+        if (k == 0) {
+            c.rec.resize(one.size());
+            for (auto& v : one) c.sizes.push_back(v.size());
+        }
+        if (one.size() != c.sizes.size()) return hipErrorInvalidValue;
+        for (size_t i = 0; i < one.size(); ++i) {
+            if (one[i].size() != c.sizes[i]) return hipErrorInvalidValue;
+            c.rec[i].insert(c.rec[i].end(), one[i].begin(), one[i].end());
+        }
+    }
+    return hipSuccess;
+}
+
+static void drop_graphs(BatchClass& c) {
+    for (int w = 0; w < 2; ++w) {
+        if (c.exec[w]) (void)hipGraphExecDestroy(c.exec[w]);
+        if (c.graph[w]) (void)hipGraphDestroy(c.graph[w]);
+        c.exec[w] = nullptr;
+        c.graph[w] = nullptr;
+    }
+}
+
+static void drop_arrays(BatchClass& c) {
+    for (void* d : c.dev) (void)hipFree(d);
+    c.dev.clear();
+}
+
+// argument arrays of the captured members (caller has synchronized the class's stream)
+static hipError_t upload_class(BatchClass& c) {
+    drop_arrays(c);
+    for (size_t i = 0; i < c.sizes.size(); ++i) {
+        const size_t sz = c.sizes[i];
+        std::vector<unsigned char> buf(sz * c.captured.size());
+        for (size_t k = 0; k < c.captured.size(); ++k)
+            std::copy_n(&c.rec[i][sz * c.captured[k]], sz, &buf[sz * k]);
+        void* d = nullptr;
+        GS_HIP_TRY(hipMalloc(&d, buf.size()));
+        c.dev.push_back(d);
+        GS_HIP_TRY(hipMemcpy(d, buf.data(), buf.size(), hipMemcpyHostToDevice));
+    }
+    return hipSuccess;
+}
+
+static hipError_t capture_class(BatchClass& c, const std::vector<BatchItem>& items, int which, int iters,
+                                hipStream_t cs) {
+    const BatchItem& rep = items[c.members[c.captured[0]]];
+    LaunchCtx ctx;
+    ctx.mode = LaunchCtx::BATCH;
+    ctx.dev = c.dev.data();
+    ctx.sizes = c.sizes.data();
+    ctx.nsites = (int)c.sizes.size();
+    ctx.count = (int)c.captured.size();
     // per-kernel timing events are host-side records: none inside a graph
     const bool prof = g_prof_enabled;
     g_prof_enabled = false;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    for (int k = 0; k < iters && e == hipSuccess; ++k) {
+        if (c.batched) {
+            ctx.site = 0;
+            g_launch = &ctx;
+        }
+        e = iterate(rep, cs);
+        g_launch = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    g_prof_enabled = prof;
     if (e != hipSuccess) {
-        g_prof_enabled = prof;
+        if (g) (void)hipGraphDestroy(g);
         return e;
     }
-    for (int k = 0; k < iters && e == hipSuccess; ++k)
-        e = it.fp32 ? cgls_iteration<float>(P, it.x, cs, hist, hist_len)
-                    : cgls_iteration<double>(P, it.x, cs, hist, hist_len);
-    hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(cs, &g);
-    g_prof_enabled = prof;
-    if (e != hipSuccess) return e;
-    if (e2 != hipSuccess) return e2;
-    it.graph[which] = g;
-    return hipGraphInstantiate(&it.exec[which], g, nullptr, nullptr, 0);
+    GS_HIP_TRY(e2);
+    c.graph[which] = g;
+    return hipGraphInstantiate(&c.exec[which], g, nullptr, nullptr, 0);
 }
 
-static void assign_streams(std::vector<BatchItem>& items, int ns) {
-    std::vector<int> order(items.size());
+static hipError_t build_class_graphs(BatchClass& c, const std::vector<BatchItem>& items, int ipg, hipStream_t cs) {
+    drop_graphs(c);
+    if (c.captured.empty()) return hipSuccess;
+    if (c.batched) GS_HIP_TRY(upload_class(c));
+    GS_HIP_TRY(capture_class(c, items, 0, 1, cs));
+    if (ipg > 1) GS_HIP_TRY(capture_class(c, items, 1, ipg, cs));
+    return hipSuccess;
+}
+
+static void assign_streams(std::vector<BatchClass>& cls, int ns) {
+    std::vector<int> order(cls.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return items[a].P->M > items[b].P->M; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cls[a].weight > cls[b].weight; });
     std::vector<double> load(ns, 0.0);
     for (int i : order) {
-        int s = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        items[i].stream = s;
-        load[s] += (double)items[i].P->M + 4.0 * items[i].P->ng * items[i].P->ng;
+        const int s = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        cls[i].stream = s;
+        load[s] += cls[i].weight;
     }
 }
 
@@ -589,58 +824,71 @@ extern "C" int gs_solve_batch(const gs_plan_t* const* plans, int count, const vo
         for (int j = 0; j < i; ++j)
             if (plans[j] == plans[i] || x[j] == x[i]) return GS_ERR_INVALID_ARG;
     }
-    const int max_streams = std::min(8, count);
     hipStream_t user = (hipStream_t)stream;
     std::vector<BatchItem> items(count);
+    std::vector<BatchClass> cls;
     std::vector<hipStream_t> streams;
-    std::vector<hipEvent_t> evs;
-    int rc = GS_OK;
+    hipEvent_t ev0 = nullptr;
     auto cleanup = [&]() {
-        for (auto& it : items)
-            for (int w = 0; w < 2; ++w) {
-                if (it.exec[w]) (void)hipGraphExecDestroy(it.exec[w]);
-                if (it.graph[w]) (void)hipGraphDestroy(it.graph[w]);
-            }
-        for (auto e : evs) (void)hipEventDestroy(e);
+        for (auto s : streams) (void)hipStreamSynchronize(s);
+        for (auto& c : cls) {
+            drop_graphs(c);
+            drop_arrays(c);
+        }
+        if (ev0) (void)hipEventDestroy(ev0);
         for (auto s : streams) (void)hipStreamDestroy(s);
     };
-    auto fail = [&](hipError_t e) {
-        (void)e;
-        for (auto s : streams) (void)hipStreamSynchronize(s);
+    auto fail = [&](hipError_t) {
         cleanup();
         return GS_ERR_HIP;
     };
-    const int ns_max = n_streams > 0 ? std::min(n_streams, count) : max_streams;
+    // classes: one per geometry on the tile path, else one per problem
+    for (int i = 0; i < count; ++i) {
+        const Plan& P = plans[i]->impl;
+        BatchItem& it = items[i];
+        it.P = &P;
+        it.x = (cx<double>*)x[i];
+        it.fp32 = P.d32.present && P.precision != GS_F64;
+        infos[i] = gs_solve_info{0, 0, GS_OK, -1.0, -1.0, 0, -1, 0};
+        int c = -1;
+        if (batchable(P))
+            for (size_t k = 0; k < cls.size() && c < 0; ++k) {
+                const Plan& Q = *items[cls[k].members[0]].P;
+                if (cls[k].batched && cls[k].fp32 == it.fp32 && Q.N == P.N && Q.ng == P.ng && Q.nb == P.nb &&
+                    Q.cr1 == P.cr1)
+                    c = (int)k;
+            }
+        if (c < 0) {
+            cls.emplace_back();
+            c = (int)cls.size() - 1;
+            cls[c].batched = batchable(P);
+            cls[c].fp32 = it.fp32;
+        }
+        it.cls = c;
+        cls[c].members.push_back(i);
+        cls[c].weight += (double)P.M + 4.0 * P.ng * P.ng;
+    }
+    const int ncls = (int)cls.size();
+    const int ns_max = n_streams > 0 ? std::min(n_streams, ncls) : std::min(8, ncls);
     for (int s = 0; s < ns_max; ++s) {
         hipStream_t h;
         if (hipStreamCreateWithFlags(&h, hipStreamNonBlocking) != hipSuccess) return fail(hipErrorUnknown);
         streams.push_back(h);
     }
-    hipEvent_t ev0;
     if (hipEventCreateWithFlags(&ev0, hipEventDisableTiming) != hipSuccess) return fail(hipErrorUnknown);
-    evs.push_back(ev0);
     if (hipEventRecord(ev0, user) != hipSuccess) return fail(hipErrorUnknown);
     for (auto s : streams)
         if (hipStreamWaitEvent(s, ev0, 0) != hipSuccess) return fail(hipErrorUnknown);
-
-    for (int i = 0; i < count; ++i) {
-        const Plan& P = plans[i]->impl;
-        items[i].P = &P;
-        items[i].x = (cx<double>*)x[i];
-        items[i].fp32 = P.d32.present && P.precision != GS_F64;
-        infos[i] = gs_solve_info{0, 0, GS_OK, -1.0, -1.0, 0};
-    }
-    assign_streams(items, ns_max);
-    // set-up of every problem, then one captured iteration graph each
+    assign_streams(cls, ns_max);
+    // set-up of every problem (plain launches on its class's stream)
     for (auto& it : items) {
-        hipStream_t s = streams[it.stream];
+        hipStream_t s = streams[cls[it.cls].stream];
         const cx<double>* yi = (const cx<double>*)y[&it - items.data()];
         int wu = 0;
-        rc = it.fp32 ? solve_setup<float>(*it.P, yi, it.x, *opts, s, &wu)
-                     : solve_setup<double>(*it.P, yi, it.x, *opts, s, &wu);
+        const int rc = it.fp32 ? solve_setup<float>(*it.P, yi, it.x, *opts, s, &wu)
+                               : solve_setup<double>(*it.P, yi, it.x, *opts, s, &wu);
         it.warm_used = wu;
         if (rc != GS_OK) {
-            for (auto st : streams) (void)hipStreamSynchronize(st);
             cleanup();
             return rc;
         }
@@ -649,30 +897,36 @@ extern "C" int gs_solve_batch(const gs_plan_t* const* plans, int count, const vo
     // iterations per graph launch: up to 16 captured back to back, the rest of
     // a check interval from the one-iteration graph
     const int ipg = std::min(check_every, 16);
-    for (auto& it : items) {
-        hipError_t e = capture_iterations(it, 0, 1, *opts, streams[it.stream]);
-        if (e == hipSuccess && ipg > 1) e = capture_iterations(it, 1, ipg, *opts, streams[it.stream]);
-        if (e != hipSuccess) return fail(e);
+    for (auto& c : cls) {
+        hipStream_t s = streams[c.stream];
+        for (size_t k = 0; k < c.members.size(); ++k) c.captured.push_back((int)k);
+        if (c.batched && record_class(c, items, s) != hipSuccess) return fail(hipErrorUnknown);
+        if (build_class_graphs(c, items, ipg, s) != hipSuccess) return fail(hipErrorUnknown);
     }
     int ns = ns_max;
     int rounds = 0;
+    auto class_active = [&](const BatchClass& c) {
+        for (int k : c.captured)
+            if (items[c.members[k]].active) return true;
+        return false;
+    };
     // n rounds: every active problem advances by n iterations
     auto run_rounds = [&](int n) -> hipError_t {
         const int full = ipg > 1 ? n / ipg : 0, rest = n - full * ipg;
         for (int r = 0; r < full; ++r)
-            for (auto& it : items)
-                if (it.active) GS_HIP_TRY(hipGraphLaunch(it.exec[1], streams[it.stream]));
+            for (auto& c : cls)
+                if (class_active(c)) GS_HIP_TRY(hipGraphLaunch(c.exec[1], streams[c.stream]));
         for (int r = 0; r < rest; ++r)
-            for (auto& it : items)
-                if (it.active) GS_HIP_TRY(hipGraphLaunch(it.exec[0], streams[it.stream]));
+            for (auto& c : cls)
+                if (class_active(c)) GS_HIP_TRY(hipGraphLaunch(c.exec[0], streams[c.stream]));
         return hipSuccess;
     };
     auto check = [&]() -> hipError_t {
         for (auto& it : items)
             if (it.active)
                 GS_HIP_TRY(hipMemcpyAsync(it.P->host_scal, it.P->scal, S_NSCAL * sizeof(double),
-                                          hipMemcpyDeviceToHost, streams[it.stream]));
-        for (int s = 0; s < ns; ++s) GS_HIP_TRY(hipStreamSynchronize(streams[s]));
+                                          hipMemcpyDeviceToHost, streams[cls[it.cls].stream]));
+        for (int s = 0; s < ns_max; ++s) GS_HIP_TRY(hipStreamSynchronize(streams[s]));
         for (auto& it : items) {
             if (!it.active) continue;
             const double* h = it.P->host_scal;
@@ -685,6 +939,16 @@ extern "C" int gs_solve_batch(const gs_plan_t* const* plans, int count, const vo
             } else if ((int)h[S_ITER] >= opts->max_iter) {
                 it.active = false;
             }
+        }
+        // classes whose graphs cover many finished problems: compact and recapture
+        for (auto& c : cls) {
+            if (!c.batched || c.captured.empty()) continue;
+            std::vector<int> keep;
+            for (int k : c.captured)
+                if (items[c.members[k]].active) keep.push_back(k);
+            if (keep.size() == c.captured.size() || 4 * keep.size() > 3 * c.captured.size()) continue;
+            c.captured = keep;
+            GS_HIP_TRY(build_class_graphs(c, items, ipg, streams[c.stream]));
         }
         return hipSuccess;
     };
@@ -702,7 +966,7 @@ extern "C" int gs_solve_batch(const gs_plan_t* const* plans, int count, const vo
             ns = cand;
             for (int s = 0; s < ns_max; ++s)
                 if (hipStreamSynchronize(streams[s]) != hipSuccess) return fail(hipErrorUnknown);
-            assign_streams(items, ns);
+            assign_streams(cls, ns);
             const auto t0 = std::chrono::steady_clock::now();
             if (run_rounds(trial) != hipSuccess) return fail(hipErrorUnknown);
             for (int s = 0; s < ns; ++s)
@@ -716,7 +980,7 @@ extern "C" int gs_solve_batch(const gs_plan_t* const* plans, int count, const vo
             if (check() != hipSuccess) return fail(hipErrorUnknown);
         }
         ns = best_ns;
-        assign_streams(items, ns);  // every stream is idle after the last check
+        assign_streams(cls, ns);  // every stream is idle after the last check
     }
     while (any_active() && rounds < opts->max_iter) {
         const int n = std::min(check_every, opts->max_iter - rounds);
@@ -732,9 +996,11 @@ extern "C" int gs_solve_batch(const gs_plan_t* const* plans, int count, const vo
         BatchItem& it = items[i];
         if (hipMemcpy(it.P->host_scal, it.P->scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
             return fail(hipErrorUnknown);
-        int r = it.fp32 ? solve_finish<float>(*it.P, it.x, *opts, infos[i], user, it.done, it.broke)
-                        : solve_finish<double>(*it.P, it.x, *opts, infos[i], user, it.done, it.broke);
+        const int r = it.fp32 ? solve_finish<float>(*it.P, it.x, *opts, infos[i], user, it.done, it.broke)
+                              : solve_finish<double>(*it.P, it.x, *opts, infos[i], user, it.done, it.broke);
         infos[i].warm_start_used = it.warm_used;
+        infos[i].batch_class = cls[it.cls].batched ? it.cls : -1;
+        infos[i].batch_streams = ns;
         // every problem is finished and reported; the call returns the worst
         // status (an error before GS_NOT_CONVERGED before GS_OK)
         if (r < 0 && worst >= 0) worst = r;
@@ -743,9 +1009,6 @@ extern "C" int gs_solve_batch(const gs_plan_t* const* plans, int count, const vo
     cleanup();
     return worst;
 }
-
-namespace gs {
-}  // namespace gs
 
 extern "C" int gs_solve(const gs_plan_t* plan, const void* y, void* x, const gs_solve_opts* opts,
                         gs_solve_info* info, void* stream);
@@ -758,7 +1021,7 @@ extern "C" int gs_solve(const gs_plan_t* plan, const void* y, void* x, const gs_
     if (opts->history && opts->history_len < 1) return GS_ERR_INVALID_ARG;
     gs_solve_info local{};
     gs_solve_info& inf = info ? *info : local;
-    inf = gs_solve_info{0, 0, GS_OK, -1.0, -1.0, 0};
+    inf = gs_solve_info{0, 0, GS_OK, -1.0, -1.0, 0, -1, 0};
     const gs::Plan& P = plan->impl;
     hipStream_t st = (hipStream_t)stream;
     if (P.d32.present && P.precision != GS_F64)

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/gs.h"
 
@@ -135,6 +136,67 @@ template <class T> inline Work<T> plan_work(const PrecData<T>& d) {
     Work<T> w;
     w.grid = d.grid; w.sr = d.sr; w.sc = d.sc; w.part = d.part; w.vbuf = d.vbuf;
     return w;
+}
+
+// ------------------------------------------------------------ launch modes
+// Each launch site of the solver's iteration passes its kernel's per-problem
+// arguments as one struct.  Normally (SINGLE) the kernel gets it by value.
+// For batched solves the same launcher code first runs once per problem in
+// RECORD mode (each site appends its struct; nothing is launched), then once
+// per class of problems of equal geometry in BATCH mode: each site launches
+// one kernel with gridDim.y = problem count, and the kernel reads problem
+// blockIdx.y's struct from a device array.  Per problem, a batched kernel does
+// exactly the arithmetic of the single launch.
+struct LaunchCtx {
+    enum Mode { SINGLE = 0, RECORD, BATCH };
+    int mode = SINGLE;
+    std::vector<std::vector<unsigned char>>* rec = nullptr;   // RECORD: per site, the structs
+    const void* const* dev = nullptr;                         // BATCH: per site, device array
+    const size_t* sizes = nullptr;                            // BATCH: per site, struct size
+    int nsites = 0;
+    int count = 0;                                            // BATCH: problems
+    int site = 0;                                             // next site
+};
+extern thread_local LaunchCtx* g_launch;
+inline bool launch_plain() { return !g_launch || g_launch->mode == LaunchCtx::SINGLE; }
+
+// go(one, many, count) launches the kernel: many == nullptr for one problem
+template <class A, class F>
+inline hipError_t launch_site(const A& a, F&& go) {
+    LaunchCtx* c = g_launch;
+    if (!c || c->mode == LaunchCtx::SINGLE) return go(a, (const A*)nullptr, 1);
+    const int i = c->site++;
+    if (c->mode == LaunchCtx::RECORD) {
+        if ((int)c->rec->size() <= i) c->rec->emplace_back();
+        std::vector<unsigned char>& v = (*c->rec)[i];
+        const unsigned char* b = reinterpret_cast<const unsigned char*>(&a);
+        v.insert(v.end(), b, b + sizeof(A));
+        return hipSuccess;
+    }
+    if (i >= c->nsites || c->sizes[i] != sizeof(A)) return hipErrorInvalidValue;
+    return go(a, static_cast<const A*>(c->dev[i]), c->count);
+}
+
+// A kernel's per-problem arguments: `one` (by value) in the single-problem
+// instance, else (BATCH) problem blockIdx.y's struct of the device array
+// `many`, read word by word into scalar registers (every lane reads the same
+// address).  The two instances share the kernel body, so a batched problem
+// gets the single launch's arithmetic.
+template <bool BATCH, class A>
+__device__ __forceinline__ A kernel_args(const A& one, const A* __restrict__ many) {
+    static_assert(sizeof(A) % 4 == 0, "argument structs are whole 32-bit words");
+    if constexpr (!BATCH) {
+        (void)many;
+        return one;
+    } else {
+        uint32_t w[sizeof(A) / 4];
+        const uint32_t* __restrict__ src = reinterpret_cast<const uint32_t*>(many + blockIdx.y);
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(A) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(src[i]);
+        A a;
+        __builtin_memcpy(&a, w, sizeof(A));
+        return a;
+    }
 }
 
 // launch helpers (defined in nfft.hip / fft.hip)

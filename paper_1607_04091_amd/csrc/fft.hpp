@@ -69,9 +69,15 @@ __device__ inline void lds_fft(cx<T>* buf, int n, int logn, int CB, const cx<T>*
     __syncthreads();
 }
 
+template <class T, class Op>
+struct FftArgs {
+    Op op;
+    const cx<T>* tw;
+};
+
 template <class T, int DIR, class Op>
-__global__ void __launch_bounds__(256) fft_kernel(Op op, const cx<T>* __restrict__ tw, int n, int logn, int CB,
-                                                 int twstride, int ntrans) {
+__device__ __forceinline__ void fft_kernel_body(const FftArgs<T, Op>& a, int n, int logn, int CB, int twstride, int ntrans) {
+    const Op& op = a.op;
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     const int t0 = blockIdx.x * CB;
@@ -80,11 +86,22 @@ __global__ void __launch_bounds__(256) fft_kernel(Op op, const cx<T>* __restrict
         const int t = t0 + c;
         buf[c * n + bitrev(i, logn)] = (t < ntrans) ? op.load(t, i) : czero<T>();
     }
-    lds_fft<T, DIR>(buf, n, logn, CB, tw, twstride);
+    lds_fft<T, DIR>(buf, n, logn, CB, a.tw, twstride);
     for (int e = threadIdx.x; e < CB * n; e += blockDim.x) {
         const int c = e % CB, k = e / CB;
         const int t = t0 + c;
         if (t < ntrans) op.store(t, k, buf[c * n + k]);
+    }
+}
+
+template <class T, int DIR, class Op, bool BATCH>
+__global__ void __launch_bounds__(256) fft_kernel(FftArgs<T, Op> one, const FftArgs<T, Op>* __restrict__ many, int n, int logn,
+                                                 int CB, int twstride, int ntrans) {
+    if constexpr (BATCH) {
+        const FftArgs<T, Op> a = kernel_args<true>(one, many);
+        fft_kernel_body<T, DIR, Op>(a, n, logn, CB, twstride, ntrans);
+    } else {
+        fft_kernel_body<T, DIR, Op>(one, n, logn, CB, twstride, ntrans);
     }
 }
 
@@ -96,9 +113,14 @@ inline hipError_t launch_fft(const Op& op, int ntrans, int n, int CB, const cx<T
     const size_t sh = (size_t)CB * n * sizeof(cx<T>);
     int threads = CB * n / 2;
     threads = threads < 64 ? 64 : (threads > 256 ? 256 : threads);
-    hipLaunchKernelGGL((fft_kernel<T, DIR, Op>), dim3(blocks), dim3(threads), sh, s, op, tw, n, logn, CB, ng / n,
-                       ntrans);
-    return hipGetLastError();
+    using A = FftArgs<T, Op>;
+    return launch_site(A{op, tw}, [&](const A& one, const A* many, int count) {
+        if (many) hipLaunchKernelGGL((fft_kernel<T, DIR, Op, true>), dim3(blocks, count), dim3(threads), sh, s, one, many, n, logn, CB,
+                           ng / n, ntrans);
+        else hipLaunchKernelGGL((fft_kernel<T, DIR, Op, false>), dim3(blocks, count), dim3(threads), sh, s, one, many, n, logn, CB,
+                           ng / n, ntrans);
+        return hipGetLastError();
+    });
 }
 
 // ------------------------------------------------------------ register FFTs
@@ -162,14 +184,23 @@ struct GridLoad {
     }
 };
 
+template <class T, class Load>
+struct ColArgs {
+    Load ld;
+    cx<T>* grid;
+    const cx<T>* tw;
+};
+
 template <class T, int R1, int R2, int DIR, class Load>
-__global__ void __launch_bounds__(256) colfft_pass1(Load ld, cx<T>* __restrict__ grid, const cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void colfft_pass1_body(const ColArgs<T, Load>& a) {
+    const Load& ld = a.ld;
+    cx<T>* __restrict__ grid = a.grid;
     constexpr int L = R1 * R2;
     __shared__ cx<T> stw[L];
-    for (int e = threadIdx.x; e < L; e += 256) stw[e] = tw[e];
+    for (int e = threadIdx.x; e < L; e += 256) stw[e] = a.tw[e];
     __syncthreads();
     const int col = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int n2 = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int n2 = blockIdx.z * 4 + (threadIdx.x >> 6);
     cx<T> v[R1];
 #pragma unroll
     for (int n1 = 0; n1 < R1; ++n1) v[n1] = ld(R2 * n1 + n2, col);
@@ -182,15 +213,31 @@ __global__ void __launch_bounds__(256) colfft_pass1(Load ld, cx<T>* __restrict__
     }
 }
 
+template <class T, int R1, int R2, int DIR, class Load, bool BATCH>
+__global__ void __launch_bounds__(256) colfft_pass1(ColArgs<T, Load> one, const ColArgs<T, Load>* __restrict__ many) {
+    if constexpr (BATCH) {
+        const ColArgs<T, Load> a = kernel_args<true>(one, many);
+        colfft_pass1_body<T, R1, R2, DIR, Load>(a);
+    } else {
+        colfft_pass1_body<T, R1, R2, DIR, Load>(one);
+    }
+}
+
+template <class T>
+struct Col2Args {
+    cx<T>* grid;
+    const cx<T>* tw;
+};
+
 template <class T, int R1, int R2, int DIR>
-__global__ void __launch_bounds__(256) colfft_pass2(cx<T>* __restrict__ grid, const cx<T>* __restrict__ tw, int N,
-                                                    int nb, int prune_out) {
+__device__ __forceinline__ void colfft_pass2_body(const Col2Args<T>& a, int N, int nb, int prune_out) {
+    cx<T>* __restrict__ grid = a.grid;
     constexpr int L = R1 * R2;
     __shared__ cx<T> stw[L];
-    for (int e = threadIdx.x; e < L; e += 256) stw[e] = tw[e];
+    for (int e = threadIdx.x; e < L; e += 256) stw[e] = a.tw[e];
     __syncthreads();
     const int col = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int k1 = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int k1 = blockIdx.z * 4 + (threadIdx.x >> 6);
     cx<T> v[R2];
 #pragma unroll
     for (int n2 = 0; n2 < R2; ++n2) v[n2] = grid[(size_t)(R2 * k1 + n2) * L + col];
@@ -202,16 +249,38 @@ __global__ void __launch_bounds__(256) colfft_pass2(cx<T>* __restrict__ grid, co
     }
 }
 
+template <class T, int R1, int R2, int DIR, bool BATCH>
+__global__ void __launch_bounds__(256) colfft_pass2(Col2Args<T> one, const Col2Args<T>* __restrict__ many, int N, int nb,
+                                                    int prune_out) {
+    if constexpr (BATCH) {
+        const Col2Args<T> a = kernel_args<true>(one, many);
+        colfft_pass2_body<T, R1, R2, DIR>(a, N, nb, prune_out);
+    } else {
+        colfft_pass2_body<T, R1, R2, DIR>(one, N, nb, prune_out);
+    }
+}
+
 // both passes; Load supplies the input of pass 1 (prune_out: inactive output rows are not stored)
 template <class T, int R1, int R2, int DIR, class Load>
 inline hipError_t launch_colfft(const Load& ld, cx<T>* grid, const cx<T>* tw, int N, int nb, int prune_out,
                                 hipStream_t s) {
     constexpr int L = R1 * R2;
-    hipLaunchKernelGGL((colfft_pass1<T, R1, R2, DIR, Load>), dim3(L / 64, R2 / 4), dim3(256), 0, s, ld, grid, tw);
-    GS_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL((colfft_pass2<T, R1, R2, DIR>), dim3(L / 64, R1 / 4), dim3(256), 0, s, grid, tw, N, nb,
-                       prune_out);
-    return hipGetLastError();
+    using A1 = ColArgs<T, Load>;
+    GS_HIP_TRY(launch_site(A1{ld, grid, tw}, [&](const A1& one, const A1* many, int count) {
+        if (many) hipLaunchKernelGGL((colfft_pass1<T, R1, R2, DIR, Load, true>), dim3(L / 64, count, R2 / 4), dim3(256), 0, s, one,
+                           many);
+        else hipLaunchKernelGGL((colfft_pass1<T, R1, R2, DIR, Load, false>), dim3(L / 64, count, R2 / 4), dim3(256), 0, s, one,
+                           many);
+        return hipGetLastError();
+    }));
+    using A2 = Col2Args<T>;
+    return launch_site(A2{grid, tw}, [&](const A2& one, const A2* many, int count) {
+        if (many) hipLaunchKernelGGL((colfft_pass2<T, R1, R2, DIR, true>), dim3(L / 64, count, R1 / 4), dim3(256), 0, s, one, many, N,
+                           nb, prune_out);
+        else hipLaunchKernelGGL((colfft_pass2<T, R1, R2, DIR, false>), dim3(L / 64, count, R1 / 4), dim3(256), 0, s, one, many, N,
+                           nb, prune_out);
+        return hipGetLastError();
+    });
 }
 
 // the column split of Plan::cr1 for grids of side ng; LoadF(L) builds the pass-1 input

@@ -96,10 +96,18 @@ template <> struct FwdThreads<float> { static constexpr int value = 1024; };
 // Interior interpolation of one tile's points (plus the boundary part, when
 // present, computed beforehand in sorted order), scales, weights and the
 // scatter to caller order.
+template <class T>
+struct InterpTileArgs {
+    TileGeo<T> g;
+    const cx<T>* grid;
+    const cx<T>* ybnd;
+    cx<T>* y;
+};
+
 template <class T, int W, int DEG, bool BND>
-__global__ void __launch_bounds__(FwdThreads<T>::value) interp_tile_kernel(TileGeo<T> g, const cx<T>* __restrict__ grid,
-                                                          const cx<T>* __restrict__ ybnd, cx<T>* __restrict__ y,
-                                                          int flags) {
+__device__ __forceinline__ void interp_tile_kernel_body(const TileGeo<T>& g, const cx<T>* __restrict__ grid,
+                                                        const cx<T>* __restrict__ ybnd, cx<T>* __restrict__ y,
+                                                        int flags) {
     constexpr int TS = TILE_TS, PW = TS + W - 1;
     __shared__ cx<T> sG[PW * PW];
     const int tile = g.order[blockIdx.x];
@@ -140,15 +148,35 @@ __global__ void __launch_bounds__(FwdThreads<T>::value) interp_tile_kernel(TileG
     }
 }
 
+template <class T, int W, int DEG, bool BND, bool BATCH>
+__global__ void __launch_bounds__(FwdThreads<T>::value) interp_tile_kernel(InterpTileArgs<T> one,
+                                                                           const InterpTileArgs<T>* many, int flags) {
+    if constexpr (BATCH) {
+        const InterpTileArgs<T> a = kernel_args<true>(one, many);
+        interp_tile_kernel_body<T, W, DEG, BND>(a.g, a.grid, a.ybnd, a.y, flags);
+    } else {
+        interp_tile_kernel_body<T, W, DEG, BND>(one.g, one.grid, one.ybnd, one.y, flags);
+    }
+}
+
 // Boundary part of T x for one tile's points (App. C): with ax_r, ay_c the
 // boundary channels of the point and Dx, Dy its interior scales,
 //   ybnd = Dy sum_r ax_r S_r + Dx sum_c ay_c C_c + sum_r ax_r sum_c X[r][c] ay_c,
 // S_r the 1D interpolation (along y) of the row-side grid r and C_c that of the
 // column-side grid c (along x).  Written in sorted order; the interior kernel adds it.
+template <class T>
+struct InterpBndArgs {
+    TileGeo<T> g;
+    const cx<T>* sr;
+    const cx<T>* sc;
+    const cx<T>* X;
+    cx<T>* ybnd;
+};
+
 template <class T, int W, int DEG, int NB>
-__global__ void __launch_bounds__(FwdThreads<T>::value) interp_bnd_kernel(TileGeo<T> g, const cx<T>* __restrict__ sr,
-                                                         const cx<T>* __restrict__ sc, const cx<T>* __restrict__ X,
-                                                         cx<T>* __restrict__ ybnd) {
+__device__ __forceinline__ void interp_bnd_kernel_body(const TileGeo<T>& g, const cx<T>* __restrict__ sr,
+                                                       const cx<T>* __restrict__ sc, const cx<T>* __restrict__ X,
+                                                       cx<T>* __restrict__ ybnd) {
     constexpr int TS = TILE_TS, PW = TS + W - 1, NCH = 2 * NB;
     __shared__ cx<T> sSR[NCH * PW];
     __shared__ cx<T> sSC[NCH * PW];
@@ -216,6 +244,17 @@ __global__ void __launch_bounds__(FwdThreads<T>::value) interp_bnd_kernel(TileGe
     }
 }
 
+template <class T, int W, int DEG, int NB, bool BATCH>
+__global__ void __launch_bounds__(FwdThreads<T>::value) interp_bnd_kernel(InterpBndArgs<T> one,
+                                                                          const InterpBndArgs<T>* many) {
+    if constexpr (BATCH) {
+        const InterpBndArgs<T> a = kernel_args<true>(one, many);
+        interp_bnd_kernel_body<T, W, DEG, NB>(a.g, a.sr, a.sc, a.X, a.ybnd);
+    } else {
+        interp_bnd_kernel_body<T, W, DEG, NB>(one.g, one.sr, one.sc, one.X, one.ybnd);
+    }
+}
+
 // ------------------------------------------------------------------ adjoint
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -279,12 +318,32 @@ __device__ inline cx<T> adj_input(const TileGeo<T>& g, const cx<T>* __restrict__
 }
 
 template <class T>
-__global__ void adj_gather_kernel(TileGeo<T> g, const cx<T>* __restrict__ u, int flags, cx<T>* __restrict__ vs) {
+struct GatherArgs {
+    TileGeo<T> g;
+    const cx<T>* u;
+    cx<T>* vs;
+};
+
+template <class T>
+__device__ __forceinline__ void adj_gather_kernel_body(const GatherArgs<T>& A, int flags) {
+    const TileGeo<T>& g = A.g;
+    const cx<T>* __restrict__ u = A.u;
+    cx<T>* __restrict__ vs = A.vs;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= g.M) return;
     cx<T> v = u[g.perm[q]];
     if (flags & GS_WEIGHTED) v = cscale(v, wscale(g.smu[q], flags));
     vs[q] = v;
+}
+
+template <class T, bool BATCH>
+__global__ void adj_gather_kernel(GatherArgs<T> one, const GatherArgs<T>* __restrict__ many, int flags) {
+    if constexpr (BATCH) {
+        const GatherArgs<T> a = kernel_args<true>(one, many);
+        adj_gather_kernel_body<T>(a, flags);
+    } else {
+        adj_gather_kernel_body<T>(one, flags);
+    }
 }
 
 // Staged bytes per workgroup.  Workgroups of more than four wavefronts run two
@@ -361,10 +420,20 @@ struct IntPre {
 // channels, spread along y); it gathers every point of the block whose cell
 // column lies in [ply-W+1, ply], reading each point once per column.  The
 // global loads of chunk k+1 are issued before chunk k is gathered.
+template <class T>
+struct AdjArgs {
+    TileGeo<T> g;
+    const cx<T>* u;
+    cx<T>* part0;   // interior: grid partials; boundary: column-side partials
+    cx<T>* part1;   // interior: row-side partials; boundary: corner partials
+};
+
 template <class T, int W, int DEG, int NB>
-__global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(TileGeo<T> g, const cx<T>* __restrict__ u, int flags,
-                                                                            cx<T>* __restrict__ partI,
-                                                                            cx<T>* __restrict__ partR) {
+__device__ __forceinline__ void adj_interior_kernel_body(const AdjArgs<T>& A, int flags) {
+    const TileGeo<T>& g = A.g;
+    const cx<T>* __restrict__ u = A.u;
+    cx<T>* __restrict__ partI = A.part0;
+    cx<T>* __restrict__ partR = A.part1;
     using L = AdjIntLDS<T, W, NB>;
     constexpr int TS = TILE_TS, RB = ADJ_RB, PW = L::PW, NRB = L::NRB, CH = L::CH, CHB = L::CHB, NCH = L::NCH;
     constexpr int NACC = RB + W - 1;
@@ -490,6 +559,17 @@ __global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(Tile
     for (int e = tid; e < PW * PW; e += NTHR) pI[e] = (&O.P[0][0])[e];
 }
 
+template <class T, int W, int DEG, int NB, bool BATCH>
+__global__ void __launch_bounds__(IntShape<W>::THREADS) adj_interior_kernel(AdjArgs<T> one, const AdjArgs<T>* __restrict__ many,
+                                                                            int flags) {
+    if constexpr (BATCH) {
+        const AdjArgs<T> a = kernel_args<true>(one, many);
+        adj_interior_kernel_body<T, W, DEG, NB>(a, flags);
+    } else {
+        adj_interior_kernel_body<T, W, DEG, NB>(one, flags);
+    }
+}
+
 // Column sides and corners of one tile (App. C, the remaining blocks of the
 // 2D matrix), with the same row-block chunked staging as the interior kernel.
 // Four wavefronts; each one
@@ -543,8 +623,11 @@ struct BndPre {
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 template <class T, int W, int DEG, int NB, int BL>
-__global__ void __launch_bounds__(BND_THREADS) __attribute__((amdgpu_waves_per_eu(2))) adj_boundary_kernel(TileGeo<T> g, const cx<T>* __restrict__ u, int flags,
-                                                                   cx<T>* __restrict__ partC, cx<T>* __restrict__ partX) {
+__device__ __forceinline__ void adj_boundary_kernel_body(const AdjArgs<T>& A, int flags) {
+    const TileGeo<T>& g = A.g;
+    const cx<T>* __restrict__ u = A.u;
+    cx<T>* __restrict__ partC = A.part0;
+    cx<T>* __restrict__ partX = A.part1;
     using L = AdjBndLDS<T, W, NB, BL>;
     constexpr int TS = TILE_TS, RB = ADJ_RB, PW = L::PW, NRB = L::NRB, NCH = L::NCH, NE = L::NE;
     constexpr int CH = L::CH, CHB = L::CHB;
@@ -744,9 +827,30 @@ __global__ void __launch_bounds__(BND_THREADS) __attribute__((amdgpu_waves_per_e
     }
 }
 
+template <class T, int W, int DEG, int NB, int BL, bool BATCH>
+__global__ void __launch_bounds__(BND_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+adj_boundary_kernel(AdjArgs<T> one, const AdjArgs<T>* __restrict__ many, int flags) {
+    if constexpr (BATCH) {
+        const AdjArgs<T> a = kernel_args<true>(one, many);
+        adj_boundary_kernel_body<T, W, DEG, NB, BL>(a, flags);
+    } else {
+        adj_boundary_kernel_body<T, W, DEG, NB, BL>(one, flags);
+    }
+}
+
 // grid cell (gx, gy) = sum of the padded tile partials that cover it (fixed order)
+template <class T>
+struct MergeGridArgs {
+    TileGeo<T> g;
+    const cx<T>* partI;
+    cx<T>* grid;
+};
+
 template <class T, int W>
-__global__ void merge_grid_kernel(TileGeo<T> g, const cx<T>* __restrict__ partI, cx<T>* __restrict__ grid) {
+__device__ __forceinline__ void merge_grid_kernel_body(const MergeGridArgs<T>& A) {
+    const TileGeo<T>& g = A.g;
+    const cx<T>* __restrict__ partI = A.partI;
+    cx<T>* __restrict__ grid = A.grid;
     constexpr int TS = TILE_TS, PW = TS + W - 1, H = W / 2 - 1;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= g.ng * g.ng) return;
@@ -764,18 +868,42 @@ __global__ void merge_grid_kernel(TileGeo<T> g, const cx<T>* __restrict__ partI,
     grid[idx] = s;
 }
 
+template <class T, int W, bool BATCH>
+__global__ void merge_grid_kernel(MergeGridArgs<T> one, const MergeGridArgs<T>* __restrict__ many) {
+    if constexpr (BATCH) {
+        const MergeGridArgs<T> a = kernel_args<true>(one, many);
+        merge_grid_kernel_body<T, W>(a);
+    } else {
+        merge_grid_kernel_body<T, W>(one);
+    }
+}
+
 // Side grids and corners from the tile partials, in a fixed order.
 //   blocks [0, nside): 32 positions gl of one side grid (row sides sr[r][gy]: the
 //     tiles of tile column gy; column sides sc[c][gx]: the tiles of tile row gx),
 //     8 thread groups each summing a fixed run of tiles, then the 8 group sums in order;
 //   blocks [nside, nside + nch^2): one corner entry X[bcol(r)][bcol(c)] over all tiles.
 constexpr int MERGE_GROUPS = 8;
+template <class T>
+struct MergeSidesArgs {
+    TileGeo<T> g;
+    const cx<T>* partR;
+    const cx<T>* partC;
+    const cx<T>* partX;
+    cx<T>* sr;
+    cx<T>* sc;
+    cx<T>* X;
+};
+
 template <class T, int W>
-__global__ void __launch_bounds__(256) merge_sides_kernel(TileGeo<T> g, const cx<T>* __restrict__ partR,
-                                                          const cx<T>* __restrict__ partC,
-                                                          const cx<T>* __restrict__ partX, int nside,
-                                                          cx<T>* __restrict__ sr, cx<T>* __restrict__ sc,
-                                                          cx<T>* __restrict__ X) {
+__device__ __forceinline__ void merge_sides_kernel_body(const MergeSidesArgs<T>& A, int nside) {
+    const TileGeo<T>& g = A.g;
+    const cx<T>* __restrict__ partR = A.partR;
+    const cx<T>* __restrict__ partC = A.partC;
+    const cx<T>* __restrict__ partX = A.partX;
+    cx<T>* __restrict__ sr = A.sr;
+    cx<T>* __restrict__ sc = A.sc;
+    cx<T>* __restrict__ X = A.X;
     constexpr int TS = TILE_TS, PW = TS + W - 1, H = W / 2 - 1;
     __shared__ cx<T> sh[256];
     const int nch = 2 * g.nb;
@@ -826,6 +954,17 @@ __global__ void __launch_bounds__(256) merge_sides_kernel(TileGeo<T> g, const cx
     }
 }
 
+template <class T, int W, bool BATCH>
+__global__ void __launch_bounds__(256) merge_sides_kernel(MergeSidesArgs<T> one, const MergeSidesArgs<T>* __restrict__ many,
+                                                          int nside) {
+    if constexpr (BATCH) {
+        const MergeSidesArgs<T> a = kernel_args<true>(one, many);
+        merge_sides_kernel_body<T, W>(a, nside);
+    } else {
+        merge_sides_kernel_body<T, W>(one, nside);
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
 template <class T>
@@ -852,14 +991,24 @@ hipError_t interp2d_tile_nb(const Plan& P, const cx<T>* x, cx<T>* y, int flags, 
     const int nt = g.ntx * g.ntx;
     if constexpr (NB > 0) {
         ProfScope _p(K_INTERP_BND, s);
-        hipLaunchKernelGGL((interp_bnd_kernel<T, W, DEG, NB>), dim3(nt), dim3(FwdThreads<T>::value), 0, s, g,
-                           (const cx<T>*)d.sr, (const cx<T>*)d.sc, x, d.ybuf);
-        GS_HIP_TRY(hipGetLastError());
+        using A = InterpBndArgs<T>;
+        GS_HIP_TRY(launch_site(A{g, d.sr, d.sc, x, d.ybuf}, [&](const A& one, const A* many, int count) {
+            if (many) hipLaunchKernelGGL((interp_bnd_kernel<T, W, DEG, NB, true>), dim3(nt, count), dim3(FwdThreads<T>::value), 0, s,
+                               one, many);
+        else hipLaunchKernelGGL((interp_bnd_kernel<T, W, DEG, NB, false>), dim3(nt, count), dim3(FwdThreads<T>::value), 0, s,
+                               one, many);
+            return hipGetLastError();
+        }));
     }
     ProfScope _p(K_INTERP2D, s);
-    hipLaunchKernelGGL((interp_tile_kernel<T, W, DEG, (NB > 0)>), dim3(nt), dim3(FwdThreads<T>::value), 0, s, g,
-                       (const cx<T>*)d.grid, (const cx<T>*)d.ybuf, y, flags);
-    return hipGetLastError();
+    using A = InterpTileArgs<T>;
+    return launch_site(A{g, d.grid, d.ybuf, y}, [&](const A& one, const A* many, int count) {
+        if (many) hipLaunchKernelGGL((interp_tile_kernel<T, W, DEG, (NB > 0), true>), dim3(nt, count), dim3(FwdThreads<T>::value), 0, s,
+                           one, many, flags);
+        else hipLaunchKernelGGL((interp_tile_kernel<T, W, DEG, (NB > 0), false>), dim3(nt, count), dim3(FwdThreads<T>::value), 0, s,
+                           one, many, flags);
+        return hipGetLastError();
+    });
 }
 
 template <class T, int NB>
@@ -874,9 +1023,18 @@ hipError_t adjoint2d_tile_nb(const Plan& P, const cx<T>* u, cx<T>* x, int flags,
     cx<T>* partC = partR + (size_t)nt * nch * PW;
     cx<T>* partX = partC + (size_t)nt * nch * PW;
     if (!(flags & GS_SORTED)) {
+        // caller-order input: per-point grids differ between problems, so batched
+        // launches take sorted input only
+        if (!launch_plain()) return hipErrorInvalidValue;
         ProfScope _p(K_ADJ_PREP, s);
-        hipLaunchKernelGGL((adj_gather_kernel<T>), dim3((P.M + 255) / 256), dim3(256), 0, s, g, u, flags, d.vbuf);
-        GS_HIP_TRY(hipGetLastError());
+        using A = GatherArgs<T>;
+        GS_HIP_TRY(launch_site(A{g, u, d.vbuf}, [&](const A& one, const A* many, int count) {
+            if (many) hipLaunchKernelGGL((adj_gather_kernel<T, true>), dim3((P.M + 255) / 256, count), dim3(256), 0, s, one, many,
+                               flags);
+        else hipLaunchKernelGGL((adj_gather_kernel<T, false>), dim3((P.M + 255) / 256, count), dim3(256), 0, s, one, many,
+                               flags);
+            return hipGetLastError();
+        }));
         u = d.vbuf;
         flags = GS_SORTED;   // gathered and weighted
     }
@@ -891,25 +1049,46 @@ hipError_t adjoint2d_tile_nb(const Plan& P, const cx<T>* u, cx<T>* x, int flags,
     if constexpr (NB > 0) {
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
         GS_HIP_TRY(hipStreamIsCapturing(s, &cap));
-        if ((std::is_same<T, double>::value || nt <= 256) && P.side && cap == hipStreamCaptureStatusNone) {
+        if ((std::is_same<T, double>::value || nt <= 256) && P.side && cap == hipStreamCaptureStatusNone &&
+            launch_plain()) {
             GS_HIP_TRY(hipEventRecord(P.ev_fork, s));
             GS_HIP_TRY(hipStreamWaitEvent(P.side, P.ev_fork, 0));
             s2 = P.side;
         }
         ProfScope _p(K_BND2D, s2);
-        if (std::is_same<T, float>::value && nt > 256)
-            hipLaunchKernelGGL((adj_boundary_kernel<T, W, DEG, NB, std::is_same<T, float>::value ? BND_LDS_FOUR : BND_LDS>),
-                               dim3(nt), dim3(BND_THREADS), 0, s2, g, u, flags, partC, partX);
-        else
-            hipLaunchKernelGGL((adj_boundary_kernel<T, W, DEG, NB, BND_LDS>), dim3(nt), dim3(BND_THREADS), 0, s2, g,
-                               u, flags, partC, partX);
-        GS_HIP_TRY(hipGetLastError());
+        using A = AdjArgs<T>;
+        GS_HIP_TRY(launch_site(A{g, u, partC, partX}, [&](const A& one, const A* many, int count) {
+            // FP32 on grids of more than 256 tiles: the 40 KB stage (four workgroups per CU)
+            constexpr int BL4 = std::is_same<T, float>::value ? BND_LDS_FOUR : BND_LDS;
+            const dim3 grid(nt, count);
+            if (std::is_same<T, float>::value && nt > 256) {
+                if (many)
+                    hipLaunchKernelGGL((adj_boundary_kernel<T, W, DEG, NB, BL4, true>), grid, dim3(BND_THREADS), 0, s2,
+                                       one, many, flags);
+                else
+                    hipLaunchKernelGGL((adj_boundary_kernel<T, W, DEG, NB, BL4, false>), grid, dim3(BND_THREADS), 0, s2,
+                                       one, many, flags);
+            } else {
+                if (many)
+                    hipLaunchKernelGGL((adj_boundary_kernel<T, W, DEG, NB, BND_LDS, true>), grid, dim3(BND_THREADS), 0,
+                                       s2, one, many, flags);
+                else
+                    hipLaunchKernelGGL((adj_boundary_kernel<T, W, DEG, NB, BND_LDS, false>), grid, dim3(BND_THREADS), 0,
+                                       s2, one, many, flags);
+            }
+            return hipGetLastError();
+        }));
     }
     {
         ProfScope _p(K_SPREAD2D, s);
-        hipLaunchKernelGGL((adj_interior_kernel<T, W, DEG, NB>), dim3(nt), dim3(IntShape<W>::THREADS), 0, s, g,
-                           u, flags, partI, partR);
-        GS_HIP_TRY(hipGetLastError());
+        using A = AdjArgs<T>;
+        GS_HIP_TRY(launch_site(A{g, u, partI, partR}, [&](const A& one, const A* many, int count) {
+            if (many) hipLaunchKernelGGL((adj_interior_kernel<T, W, DEG, NB, true>), dim3(nt, count), dim3(IntShape<W>::THREADS), 0, s,
+                               one, many, flags);
+        else hipLaunchKernelGGL((adj_interior_kernel<T, W, DEG, NB, false>), dim3(nt, count), dim3(IntShape<W>::THREADS), 0, s,
+                               one, many, flags);
+            return hipGetLastError();
+        }));
     }
     if (s2 != s) {
         GS_HIP_TRY(hipEventRecord(P.ev_join, s2));
@@ -917,14 +1096,24 @@ hipError_t adjoint2d_tile_nb(const Plan& P, const cx<T>* u, cx<T>* x, int flags,
     }
     {
         ProfScope _p(K_MERGE, s);
-        hipLaunchKernelGGL((merge_grid_kernel<T, W>), dim3((g.ng * g.ng + 255) / 256), dim3(256), 0, s, g, partI,
-                           d.grid);
-        GS_HIP_TRY(hipGetLastError());
+        using A = MergeGridArgs<T>;
+        GS_HIP_TRY(launch_site(A{g, partI, d.grid}, [&](const A& one, const A* many, int count) {
+            if (many) hipLaunchKernelGGL((merge_grid_kernel<T, W, true>), dim3((g.ng * g.ng + 255) / 256, count), dim3(256), 0, s, one,
+                               many);
+        else hipLaunchKernelGGL((merge_grid_kernel<T, W, false>), dim3((g.ng * g.ng + 255) / 256, count), dim3(256), 0, s, one,
+                               many);
+            return hipGetLastError();
+        }));
         if (NB > 0) {
             const int nside = 2 * nch * (g.ng / 32);
-            hipLaunchKernelGGL((merge_sides_kernel<T, W>), dim3(nside + nch * nch), dim3(256), 0, s, g, partR, partC,
-                               partX, nside, d.sr, d.sc, x);
-            GS_HIP_TRY(hipGetLastError());
+            using B = MergeSidesArgs<T>;
+            GS_HIP_TRY(launch_site(B{g, partR, partC, partX, d.sr, d.sc, x}, [&](const B& one, const B* many, int count) {
+                if (many) hipLaunchKernelGGL((merge_sides_kernel<T, W, true>), dim3(nside + nch * nch, count), dim3(256), 0, s, one, many,
+                                   nside);
+        else hipLaunchKernelGGL((merge_sides_kernel<T, W, false>), dim3(nside + nch * nch, count), dim3(256), 0, s, one, many,
+                                   nside);
+                return hipGetLastError();
+            }));
         }
     }
     return hipSuccess;

@@ -64,7 +64,7 @@ class SolveOpts(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("status", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("rel_residual_fp64", ctypes.c_double),
-                ("warm_start_used", ctypes.c_int)]
+                ("warm_start_used", ctypes.c_int), ("batch_class", ctypes.c_int), ("batch_streams", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -435,7 +435,8 @@ def gs_solve_batch(plans, ys, xs=None, rel_tol=1e-6, max_iter=500, refine_fp64=T
         raise GSError(rc, "gs_solve_batch")
     res = [{"status": i.status, "iterations": i.iterations, "restarts": i.restarts,
             "rel_residual": i.rel_residual, "rel_residual_fp64": i.rel_residual_fp64,
-            "warm_start_used": bool(i.warm_start_used)} for i in infos]
+            "warm_start_used": bool(i.warm_start_used), "batch_class": i.batch_class,
+            "batch_streams": i.batch_streams} for i in infos]
     return xs, res
 
 

@@ -159,3 +159,34 @@ def test_batch_first_member_fails():
     _same((xs, infos), lone)
     for pl in plans:
         pl.destroy()
+
+
+@pytest.mark.parametrize("n_streams,check_every", [(1, 1), (0, 4)])
+def test_batch_classes_of_equal_geometry(n_streams, check_every):
+    """Several problems per geometry class (2D, same N, p and precision;
+    different point sets and counts): each class runs every kernel as one
+    launch for all its active problems, and finished problems leave the
+    launches.  Every result still equals its lone solve bit for bit."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1607_04091_amd import gs
+    specs = [(5, 4, 2)] * 4 + [(6, 2, 0)] * 3 + [(6, 4, 2)]
+    plans, ys = [], []
+    rng = np.random.default_rng(660)
+    for k, (J, p, prec) in enumerate(specs):
+        N = 1 << J
+        M = int(rng.integers(3, 5) * N * N)
+        pts = jitter_2d(M, N * rng.uniform(0.6, 1.0), 670 + k)
+        plans.append(gs.gs_plan(2, J, p, pts, rng.uniform(0.5, 1.5, pts.shape[0]), precision=prec))
+        ys.append(to_dev(crandn(np.random.default_rng(680 + k), pts.shape[0]), torch.complex128))
+    say(f"[batch classes] n_streams={n_streams} check_every={check_every}")
+    lone = _lone(gs, plans, ys, rel_tol=1e-6, max_iter=300)
+    xs, infos = gs.gs_solve_batch(plans, ys, rel_tol=1e-6, max_iter=300, refine_fp64=True, max_restarts=3,
+                                  check_every=check_every, n_streams=n_streams)
+    cl = [i["batch_class"] for i in infos]
+    say(f"  classes {cl}, iterations {[i['iterations'] for i in infos]}, streams {infos[0]['batch_streams']}")
+    assert len(set(cl[:4])) == 1 and len(set(cl[4:7])) == 1 and cl[7] not in cl[:7] and min(cl) >= 0
+    assert len({i["iterations"] for i in infos[:4]}) > 1          # members finish at different rounds
+    _same((xs, infos), lone)
+    for pl in plans:
+        pl.destroy()
