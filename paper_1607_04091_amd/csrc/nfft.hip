@@ -19,7 +19,9 @@
 
 namespace gs {
 
-template <class T> hipError_t interp2d_tile(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hipStream_t s);
+// part: 1 = boundary blocks only, 2 = interior (adds the boundary part), 3 = both
+template <class T> hipError_t interp2d_tile(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hipStream_t s,
+                                            int part = 3);
 template <class T> hipError_t adjoint2d_tile(const Plan& P, const cx<T>* u, cx<T>* x, int flags, hipStream_t s,
                                              const Work<T>& wk);
 size_t adjoint2d_part_elems(int ng, int ts, int nb, int w);
@@ -559,6 +561,7 @@ hipError_t launch_apply_T(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hi
     const PrecData<T>& d = prec<T>(P);
     const Geo<T> g = make_geo<T>(P);
     const int N = P.N, nb = P.nb, ng = P.ng;
+    const bool tiled = P.dim == 2 && P.ts == TILE;
     if (P.dim == 2) {
         const OpT2Rows<T> rows{x, d.grid, d.sr, d.deap, N, nb, ng};
         if (nb) {
@@ -587,7 +590,7 @@ hipError_t launch_apply_T(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hi
                                                            ng, s))));
         }
     }
-    if (P.dim == 2 && P.ts == TILE) return interp2d_tile<T>(P, x, y, flags, s);
+    if (tiled) return interp2d_tile<T>(P, x, y, flags, s);
     return dispatch_interp<T>(P, g, x, y, flags, s);
 }
 

@@ -329,11 +329,23 @@ __device__ __forceinline__ void adj_gather_kernel_body(const GatherArgs<T>& A, i
     const TileGeo<T>& g = A.g;
     const cx<T>* __restrict__ u = A.u;
     cx<T>* __restrict__ vs = A.vs;
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= g.M) return;
-    cx<T> v = u[g.perm[q]];
-    if (flags & GS_WEIGHTED) v = cscale(v, wscale(g.smu[q], flags));
-    vs[q] = v;
+    // four points per thread: their random reads of u are in flight together
+    const int q0 = 4 * (blockIdx.x * blockDim.x + threadIdx.x);
+    if (q0 >= g.M) return;
+    const int n = min(4, g.M - q0);
+    int m[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m[i] = i < n ? g.perm[q0 + i] : 0;
+    cx<T> v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = u[m[i]];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (i >= n) break;
+        cx<T> w = v[i];
+        if (flags & GS_WEIGHTED) w = cscale(w, wscale(g.smu[q0 + i], flags));
+        vs[q0 + i] = w;
+    }
 }
 
 template <class T, bool BATCH>
@@ -847,12 +859,12 @@ struct MergeGridArgs {
 };
 
 template <class T, int W>
-__device__ __forceinline__ void merge_grid_kernel_body(const MergeGridArgs<T>& A) {
+__device__ __forceinline__ void merge_grid_kernel_body(const MergeGridArgs<T>& A, int bid) {
     const TileGeo<T>& g = A.g;
     const cx<T>* __restrict__ partI = A.partI;
     cx<T>* __restrict__ grid = A.grid;
     constexpr int TS = TILE_TS, PW = TS + W - 1, H = W / 2 - 1;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int idx = bid * blockDim.x + threadIdx.x;
     if (idx >= g.ng * g.ng) return;
     const int gx = idx >> g.G, gy = idx & g.mask;
     const int sx = (gx + H) & g.mask, sy = (gy + H) & g.mask;
@@ -872,9 +884,9 @@ template <class T, int W, bool BATCH>
 __global__ void merge_grid_kernel(MergeGridArgs<T> one, const MergeGridArgs<T>* __restrict__ many) {
     if constexpr (BATCH) {
         const MergeGridArgs<T> a = kernel_args<true>(one, many);
-        merge_grid_kernel_body<T, W>(a);
+        merge_grid_kernel_body<T, W>(a, blockIdx.x);
     } else {
-        merge_grid_kernel_body<T, W>(one);
+        merge_grid_kernel_body<T, W>(one, blockIdx.x);
     }
 }
 
@@ -896,7 +908,7 @@ struct MergeSidesArgs {
 };
 
 template <class T, int W>
-__device__ __forceinline__ void merge_sides_kernel_body(const MergeSidesArgs<T>& A, int nside) {
+__device__ __forceinline__ void merge_sides_kernel_body(const MergeSidesArgs<T>& A, int nside, int bid) {
     const TileGeo<T>& g = A.g;
     const cx<T>* __restrict__ partR = A.partR;
     const cx<T>* __restrict__ partC = A.partC;
@@ -908,8 +920,8 @@ __device__ __forceinline__ void merge_sides_kernel_body(const MergeSidesArgs<T>&
     __shared__ cx<T> sh[256];
     const int nch = 2 * g.nb;
     const int tid = threadIdx.x;
-    if ((int)blockIdx.x >= nside) {
-        const int e = blockIdx.x - nside;   // (r, c)
+    if (bid >= nside) {
+        const int e = bid - nside;   // (r, c)
         const int nt = g.ntx * g.ntx;
         cx<T> s = czero<T>();
         for (int t = tid; t < nt; t += 256) s = cadd(s, partX[(size_t)t * nch * nch + e]);
@@ -923,9 +935,9 @@ __device__ __forceinline__ void merge_sides_kernel_body(const MergeSidesArgs<T>&
         return;
     }
     const int per = g.ng / 32;                      // blocks per side grid
-    const int which = blockIdx.x / (nch * per);
-    const int r = (blockIdx.x / per) % nch;
-    const int gl = (blockIdx.x % per) * 32 + (tid & 31);
+    const int which = bid / (nch * per);
+    const int r = (bid / per) % nch;
+    const int gl = (bid % per) * 32 + (tid & 31);
     const int grp = tid >> 5;
     const int sl = (gl + H) & g.mask;
     const int t0 = sl >> g.lts, p0 = sl & (TS - 1);
@@ -959,9 +971,31 @@ __global__ void __launch_bounds__(256) merge_sides_kernel(MergeSidesArgs<T> one,
                                                           int nside) {
     if constexpr (BATCH) {
         const MergeSidesArgs<T> a = kernel_args<true>(one, many);
-        merge_sides_kernel_body<T, W>(a, nside);
+        merge_sides_kernel_body<T, W>(a, nside, blockIdx.x);
     } else {
-        merge_sides_kernel_body<T, W>(one, nside);
+        merge_sides_kernel_body<T, W>(one, nside, blockIdx.x);
+    }
+}
+
+// Grid and side merges in one launch: blocks [0, ngrid) merge the grid, the
+// rest the side grids and corners.
+template <class T>
+struct MergeArgs {
+    MergeGridArgs<T> grid;
+    MergeSidesArgs<T> sides;
+};
+
+template <class T, int W, bool BATCH>
+__global__ void __launch_bounds__(256) merge_kernel(MergeArgs<T> one, const MergeArgs<T>* many, int ngrid,
+                                                    int nside) {
+    const int bid = blockIdx.x;
+    if constexpr (BATCH) {
+        const MergeArgs<T> a = kernel_args<true>(one, many);
+        if (bid < ngrid) merge_grid_kernel_body<T, W>(a.grid, bid);
+        else merge_sides_kernel_body<T, W>(a.sides, nside, bid - ngrid);
+    } else {
+        if (bid < ngrid) merge_grid_kernel_body<T, W>(one.grid, bid);
+        else merge_sides_kernel_body<T, W>(one.sides, nside, bid - ngrid);
     }
 }
 
@@ -984,12 +1018,12 @@ template <> struct TileWin<float> { static constexpr int W = W32, DEG = DEG32; }
 template <> struct TileWin<double> { static constexpr int W = W64, DEG = DEG64; };
 
 template <class T, int NB>
-hipError_t interp2d_tile_nb(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hipStream_t s) {
+hipError_t interp2d_tile_nb(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hipStream_t s, int part) {
     const PrecData<T>& d = prec<T>(P);
     const TileGeo<T> g = make_tile_geo<T>(P);
     constexpr int W = TileWin<T>::W, DEG = TileWin<T>::DEG;
     const int nt = g.ntx * g.ntx;
-    if constexpr (NB > 0) {
+    if constexpr (NB > 0) if (part & 1) {
         ProfScope _p(K_INTERP_BND, s);
         using A = InterpBndArgs<T>;
         GS_HIP_TRY(launch_site(A{g, d.sr, d.sc, x, d.ybuf}, [&](const A& one, const A* many, int count) {
@@ -1000,6 +1034,7 @@ hipError_t interp2d_tile_nb(const Plan& P, const cx<T>* x, cx<T>* y, int flags, 
             return hipGetLastError();
         }));
     }
+    if (!(part & 2)) return hipSuccess;
     ProfScope _p(K_INTERP2D, s);
     using A = InterpTileArgs<T>;
     return launch_site(A{g, d.grid, d.ybuf, y}, [&](const A& one, const A* many, int count) {
@@ -1029,9 +1064,9 @@ hipError_t adjoint2d_tile_nb(const Plan& P, const cx<T>* u, cx<T>* x, int flags,
         ProfScope _p(K_ADJ_PREP, s);
         using A = GatherArgs<T>;
         GS_HIP_TRY(launch_site(A{g, u, d.vbuf}, [&](const A& one, const A* many, int count) {
-            if (many) hipLaunchKernelGGL((adj_gather_kernel<T, true>), dim3((P.M + 255) / 256, count), dim3(256), 0, s, one, many,
+            if (many) hipLaunchKernelGGL((adj_gather_kernel<T, true>), dim3((P.M + 1023) / 1024, count), dim3(256), 0, s, one, many,
                                flags);
-        else hipLaunchKernelGGL((adj_gather_kernel<T, false>), dim3((P.M + 255) / 256, count), dim3(256), 0, s, one, many,
+        else hipLaunchKernelGGL((adj_gather_kernel<T, false>), dim3((P.M + 1023) / 1024, count), dim3(256), 0, s, one, many,
                                flags);
             return hipGetLastError();
         }));
@@ -1096,22 +1131,29 @@ hipError_t adjoint2d_tile_nb(const Plan& P, const cx<T>* u, cx<T>* x, int flags,
     }
     {
         ProfScope _p(K_MERGE, s);
-        using A = MergeGridArgs<T>;
-        GS_HIP_TRY(launch_site(A{g, partI, d.grid}, [&](const A& one, const A* many, int count) {
-            if (many) hipLaunchKernelGGL((merge_grid_kernel<T, W, true>), dim3((g.ng * g.ng + 255) / 256, count), dim3(256), 0, s, one,
-                               many);
-        else hipLaunchKernelGGL((merge_grid_kernel<T, W, false>), dim3((g.ng * g.ng + 255) / 256, count), dim3(256), 0, s, one,
-                               many);
-            return hipGetLastError();
-        }));
-        if (NB > 0) {
+        const int ngrid = (g.ng * g.ng + 255) / 256;
+        if constexpr (NB > 0) {
             const int nside = 2 * nch * (g.ng / 32);
-            using B = MergeSidesArgs<T>;
-            GS_HIP_TRY(launch_site(B{g, partR, partC, partX, d.sr, d.sc, x}, [&](const B& one, const B* many, int count) {
-                if (many) hipLaunchKernelGGL((merge_sides_kernel<T, W, true>), dim3(nside + nch * nch, count), dim3(256), 0, s, one, many,
-                                   nside);
-        else hipLaunchKernelGGL((merge_sides_kernel<T, W, false>), dim3(nside + nch * nch, count), dim3(256), 0, s, one, many,
-                                   nside);
+            using A = MergeArgs<T>;
+            GS_HIP_TRY(launch_site(A{MergeGridArgs<T>{g, partI, d.grid},
+                                     MergeSidesArgs<T>{g, partR, partC, partX, d.sr, d.sc, x}},
+                                   [&](const A& one, const A* many, int count) {
+                                       const dim3 grid(ngrid + nside + nch * nch, count);
+                                       if (many)
+                                           hipLaunchKernelGGL((merge_kernel<T, W, true>), grid, dim3(256), 0, s, one,
+                                                              many, ngrid, nside);
+                                       else
+                                           hipLaunchKernelGGL((merge_kernel<T, W, false>), grid, dim3(256), 0, s, one,
+                                                              many, ngrid, nside);
+                                       return hipGetLastError();
+                                   }));
+        } else {
+            using A = MergeGridArgs<T>;
+            GS_HIP_TRY(launch_site(A{g, partI, d.grid}, [&](const A& one, const A* many, int count) {
+                if (many)
+                    hipLaunchKernelGGL((merge_grid_kernel<T, W, true>), dim3(ngrid, count), dim3(256), 0, s, one, many);
+                else
+                    hipLaunchKernelGGL((merge_grid_kernel<T, W, false>), dim3(ngrid, count), dim3(256), 0, s, one, many);
                 return hipGetLastError();
             }));
         }
@@ -1120,16 +1162,16 @@ hipError_t adjoint2d_tile_nb(const Plan& P, const cx<T>* u, cx<T>* x, int flags,
 }
 
 template <class T>
-hipError_t interp2d_tile(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hipStream_t s) {
+hipError_t interp2d_tile(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hipStream_t s, int part) {
     switch (P.nb) {
-        case 0: return interp2d_tile_nb<T, 0>(P, x, y, flags, s);
-        case 2: return interp2d_tile_nb<T, 2>(P, x, y, flags, s);
-        case 3: return interp2d_tile_nb<T, 3>(P, x, y, flags, s);
-        case 4: return interp2d_tile_nb<T, 4>(P, x, y, flags, s);
-        case 5: return interp2d_tile_nb<T, 5>(P, x, y, flags, s);
-        case 6: return interp2d_tile_nb<T, 6>(P, x, y, flags, s);
-        case 7: return interp2d_tile_nb<T, 7>(P, x, y, flags, s);
-        case 8: return interp2d_tile_nb<T, 8>(P, x, y, flags, s);
+        case 0: return interp2d_tile_nb<T, 0>(P, x, y, flags, s, part);
+        case 2: return interp2d_tile_nb<T, 2>(P, x, y, flags, s, part);
+        case 3: return interp2d_tile_nb<T, 3>(P, x, y, flags, s, part);
+        case 4: return interp2d_tile_nb<T, 4>(P, x, y, flags, s, part);
+        case 5: return interp2d_tile_nb<T, 5>(P, x, y, flags, s, part);
+        case 6: return interp2d_tile_nb<T, 6>(P, x, y, flags, s, part);
+        case 7: return interp2d_tile_nb<T, 7>(P, x, y, flags, s, part);
+        case 8: return interp2d_tile_nb<T, 8>(P, x, y, flags, s, part);
     }
     return hipErrorInvalidValue;
 }
@@ -1149,8 +1191,8 @@ hipError_t adjoint2d_tile(const Plan& P, const cx<T>* u, cx<T>* x, int flags, hi
     return hipErrorInvalidValue;
 }
 
-template hipError_t interp2d_tile<float>(const Plan&, const cx<float>*, cx<float>*, int, hipStream_t);
-template hipError_t interp2d_tile<double>(const Plan&, const cx<double>*, cx<double>*, int, hipStream_t);
+template hipError_t interp2d_tile<float>(const Plan&, const cx<float>*, cx<float>*, int, hipStream_t, int);
+template hipError_t interp2d_tile<double>(const Plan&, const cx<double>*, cx<double>*, int, hipStream_t, int);
 template hipError_t adjoint2d_tile<float>(const Plan&, const cx<float>*, cx<float>*, int, hipStream_t,
                                           const Work<float>&);
 template hipError_t adjoint2d_tile<double>(const Plan&, const cx<double>*, cx<double>*, int, hipStream_t,
