@@ -23,11 +23,18 @@ constexpr int RB = 512;      // reduction blocks (fixed -> deterministic)
 constexpr int RT = 256;      // threads per reduction block
 
 // S_GMIN: smallest gamma of the current run; S_GROW: stall factor (0 = off);
-// S_STALL: the run stopped because gamma rose above S_GROW * S_GMIN
+// S_STALL: the run stopped because gamma rose above S_GROW * S_GMIN.
+// The four scalars the iteration advances (gamma, done, break, gmin) have two
+// copies: workgroup 0 of update_p writes the first (the step of the
+// iteration) while its other workgroups read only the second, which workgroup
+// 0 of update_xr refreshes from the first while its workgroups read only the
+// first.  No workgroup reads a slot its own kernel writes.
 enum Scal {
     S_GAMMA = 0, S_DELTA, S_ALPHA, S_REF, S_TOL2, S_DONE, S_BREAK, S_ITER, S_REF64, S_GMIN, S_GROW, S_STALL,
+    S_GAMMA_B, S_DONE_B, S_BREAK_B, S_GMIN_B,
     S_NSCAL = 16
 };
+static_assert(S_GMIN_B < S_NSCAL, "scalar slots");
 
 template <class T> __device__ inline cx<double> to64(cx<T> v) { return mk<double>((double)v.x, (double)v.y); }
 
@@ -43,10 +50,10 @@ __device__ inline double block_sum(double v, double* sh) {
     return r;
 }
 
-// sum of the RB partials, same order in every block
-__device__ inline double sum_partials(const double* __restrict__ red, double* sh) {
+// sum of n partials, same order in every block
+__device__ inline double sum_partials(const double* __restrict__ red, int n, double* sh) {
     double v = 0;
-    for (int i = threadIdx.x; i < RB; i += RT) v += red[i];
+    for (int i = threadIdx.x; i < n; i += RT) v += red[i];
     return block_sum(v, sh);
 }
 
@@ -130,10 +137,10 @@ __global__ void init_p_kernel(const cx<T>* __restrict__ s, cx<double>* __restric
 }
 
 // scalar setup after the first A^H r: gamma, ref, done flag
-__global__ void start_scalars_kernel(double* __restrict__ scal, const double* __restrict__ red, int set_ref,
+__global__ void start_scalars_kernel(double* __restrict__ scal, const double* __restrict__ red, int nred, int set_ref,
                                      double* __restrict__ hist, int hist_len) {
     __shared__ double sh[RT];
-    const double g = sum_partials(red, sh);
+    const double g = sum_partials(red, nred, sh);
     if (threadIdx.x == 0) {
         scal[S_GAMMA] = g;
         if (set_ref) scal[S_REF] = sqrt(g);
@@ -149,7 +156,7 @@ __global__ void start_scalars_kernel(double* __restrict__ scal, const double* __
 
 __global__ void set_ref64_kernel(double* __restrict__ scal, const double* __restrict__ red) {
     __shared__ double sh[RT];
-    const double g = sum_partials(red, sh);
+    const double g = sum_partials(red, RB, sh);
     if (threadIdx.x == 0) scal[S_REF64] = sqrt(g);
 }
 
@@ -158,6 +165,7 @@ template <class T, class Tr>
 struct UpdateXrArgs {
     double* scal;
     const double* red;
+    int nred;
     cx<double>* x;
     const cx<double>* p;
     int64_t nx;
@@ -179,11 +187,18 @@ __device__ __forceinline__ void update_xr_kernel_body(const UpdateXrArgs<T, Tr>&
     cx<Tr>* __restrict__ rT = A.rT;
     const int64_t M = A.M;
     __shared__ double sh[RT];
-    const double delta = sum_partials(red, sh);
-    if (scal[S_DONE] != 0.0) return;
+    const double delta = sum_partials(red, A.nred, sh);
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (lead) {
+        scal[S_GAMMA_B] = scal[S_GAMMA];
+        scal[S_DONE_B] = scal[S_DONE];
+        scal[S_BREAK_B] = scal[S_BREAK];
+        scal[S_GMIN_B] = scal[S_GMIN];
+    }
+    if (scal[S_DONE] != 0.0 || scal[S_BREAK] != 0.0) return;
     const double alpha = scal[S_GAMMA] / delta;
     if (!(delta > 0.0) || !isfinite(delta) || !isfinite(alpha)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_BREAK] = 1.0;
+        if (lead) scal[S_BREAK_B] = 1.0;
         return;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -220,14 +235,18 @@ __global__ void __launch_bounds__(RT) update_xr_kernel(UpdateXrArgs<T, Tr> one, 
     }
 }
 
-// p = s + beta p, beta = ||s||^2 / gamma (gamma not yet updated).  With
-// xbest (reduced-precision recurrences), x is also copied there whenever its
-// normal residual ||s||^2 is the smallest of the run, so that a recurrence
-// stopped past its accuracy floor can return its best iterate.
+// p = s + beta p, beta = ||s||^2 / gamma.  With xbest (reduced-precision
+// recurrences), x is also copied there whenever its normal residual ||s||^2
+// is the smallest of the run, so that a recurrence stopped past its accuracy
+// floor can return its best iterate.  Workgroup 0 then takes the step of the
+// scalars: gamma = ||s||^2, iteration count, history, convergence test.
 template <class T, class Tp>
 struct UpdatePArgs {
-    const double* scal;
+    double* scal;
     const double* red;
+    int nred;
+    double* hist;
+    int hist_len;
     cx<double>* p;
     const cx<T>* s;
     cx<Tp>* pT;
@@ -238,7 +257,7 @@ struct UpdatePArgs {
 
 template <class T, class Tp>
 __device__ __forceinline__ void update_p_kernel_body(const UpdatePArgs<T, Tp>& A) {
-    const double* __restrict__ scal = A.scal;
+    double* __restrict__ scal = A.scal;
     const double* __restrict__ red = A.red;
     cx<double>* __restrict__ p = A.p;
     const cx<T>* __restrict__ s = A.s;
@@ -247,10 +266,19 @@ __device__ __forceinline__ void update_p_kernel_body(const UpdatePArgs<T, Tp>& A
     const cx<double>* __restrict__ x = A.x;
     cx<double>* __restrict__ xbest = A.xbest;
     __shared__ double sh[RT];
-    const double gnew = sum_partials(red, sh);
-    if (scal[S_DONE] != 0.0 || scal[S_BREAK] != 0.0) return;
-    const double beta = gnew / scal[S_GAMMA];
-    const bool keep = xbest && gnew < scal[S_GMIN];
+    const double gnew = sum_partials(red, A.nred, sh);
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (scal[S_DONE_B] != 0.0) return;
+    if (scal[S_BREAK_B] != 0.0) {
+        if (lead) {
+            scal[S_BREAK] = 1.0;
+            scal[S_DONE] = 1.0;
+        }
+        return;
+    }
+    const double gmin = scal[S_GMIN_B];
+    const double beta = gnew / scal[S_GAMMA_B];
+    const bool keep = xbest && gnew < gmin;
     for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < nx; i += (int64_t)gridDim.x * RT) {
         const cx<double> sv = to64(s[i]);
         cx<double> pv = p[i];
@@ -260,6 +288,21 @@ __device__ __forceinline__ void update_p_kernel_body(const UpdatePArgs<T, Tp>& A
         if (pT) pT[i] = mk<Tp>((Tp)pv.x, (Tp)pv.y);
         if (keep) xbest[i] = x[i];
     }
+    if (!lead) return;
+    scal[S_GAMMA] = gnew;
+    const double it = scal[S_ITER] + 1.0;
+    scal[S_ITER] = it;
+    const double ref = scal[S_REF];
+    if (A.hist && (int)it < A.hist_len) A.hist[(int)it] = sqrt(gnew) / ref;
+    if (gnew <= scal[S_TOL2] * ref * ref) {
+        scal[S_DONE] = 1.0;
+    } else if (scal[S_GROW] > 0.0 && !(gnew <= scal[S_GROW] * gmin)) {
+        // reduced-precision recurrence past its accuracy floor: stop it here
+        scal[S_STALL] = 1.0;
+        scal[S_BREAK] = 1.0;
+        scal[S_DONE] = 1.0;
+    }
+    scal[S_GMIN] = fmin(gmin, gnew);
 }
 
 template <class T, class Tp, bool BATCH>
@@ -275,53 +318,6 @@ __global__ void __launch_bounds__(RT) update_p_kernel(UpdatePArgs<T, Tp> one, co
 __global__ void copy_kernel(const cx<double>* __restrict__ a, cx<double>* __restrict__ o, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) o[i] = a[i];
-}
-
-// gamma = ||s||^2 ; iteration count, history, convergence test
-struct StepArgs {
-    double* scal;
-    const double* red;
-    double* hist;
-    int hist_len;
-};
-
-__device__ __forceinline__ void step_scalars_kernel_body(const StepArgs& A) {
-    double* __restrict__ scal = A.scal;
-    const double* __restrict__ red = A.red;
-    double* __restrict__ hist = A.hist;
-    const int hist_len = A.hist_len;
-    __shared__ double sh[RT];
-    const double gnew = sum_partials(red, sh);
-    if (threadIdx.x != 0) return;
-    if (scal[S_DONE] != 0.0) return;
-    if (scal[S_BREAK] != 0.0) {
-        scal[S_DONE] = 1.0;
-        return;
-    }
-    scal[S_GAMMA] = gnew;
-    const double it = scal[S_ITER] + 1.0;
-    scal[S_ITER] = it;
-    const double ref = scal[S_REF];
-    if (hist && (int)it < hist_len) hist[(int)it] = sqrt(gnew) / ref;
-    if (gnew <= scal[S_TOL2] * ref * ref) {
-        scal[S_DONE] = 1.0;
-    } else if (scal[S_GROW] > 0.0 && !(gnew <= scal[S_GROW] * scal[S_GMIN])) {
-        // reduced-precision recurrence past its accuracy floor: stop it here
-        scal[S_STALL] = 1.0;
-        scal[S_BREAK] = 1.0;
-        scal[S_DONE] = 1.0;
-    }
-    scal[S_GMIN] = fmin(scal[S_GMIN], gnew);
-}
-
-template <bool BATCH>
-__global__ void step_scalars_kernel(StepArgs one, const StepArgs* __restrict__ many) {
-    if constexpr (BATCH) {
-        const StepArgs a = kernel_args<true>(one, many);
-        step_scalars_kernel_body(a);
-    } else {
-        step_scalars_kernel_body(one);
-    }
 }
 
 __global__ void set_scalar_kernel(double* __restrict__ scal, int idx, double v) {
@@ -363,8 +359,8 @@ hipError_t solver_alloc(Plan& P) {
         GS_HIP_TRY(alloc(P.p32, nx));
         GS_HIP_TRY(alloc(P.s32, nx));
     }
-    P.red_blocks = RB;
-    GS_HIP_TRY(alloc(P.red, (size_t)RB));
+    P.red_blocks = std::max(RB, norm_parts_TH(P));
+    GS_HIP_TRY(alloc(P.red, (size_t)P.red_blocks));
     GS_HIP_TRY(alloc(P.scal, (size_t)S_NSCAL));
     P.hist_len = 1 << 16;
     GS_HIP_TRY(alloc(P.hist, (size_t)P.hist_len));
@@ -405,6 +401,26 @@ struct Ops<float> {
 
 constexpr int AFLAGS = GS_WEIGHTED | GS_SORTED;
 
+// q = A p with ||q||^2 as RB partial sums in P.red, and s = A^H r with
+// ||s||^2 as partial sums in P.red: written by the adjoint's last launch
+// where its path provides them, else by a separate reduction.  Returns the
+// number of partials through nred.
+template <class T>
+hipError_t apply_T_norm(const Plan& P, const cx<T>* x, cx<T>* y, hipStream_t st, int& nred) {
+    GS_HIP_TRY(launch_apply_T<T>(P, x, y, AFLAGS, st));
+    GS_HIP_TRY(launch_norm2<T>(y, P.M, P.red, st));
+    nred = RB;
+    return hipSuccess;
+}
+template <class T>
+hipError_t apply_TH_norm(const Plan& P, const cx<T>* u, cx<T>* x, hipStream_t st, int& nred) {
+    const int n = norm_parts_TH(P);
+    GS_HIP_TRY(launch_apply_TH<T>(P, u, x, AFLAGS, st, nullptr, n ? P.red : nullptr));
+    if (!n) GS_HIP_TRY(launch_norm2<T>(x, P.dim == 2 ? (int64_t)P.N * P.N : P.N, P.red, st));
+    nred = n ? n : RB;
+    return hipSuccess;
+}
+
 // Starts CGLS from x (already on device, FP64) given r = b - A x in P.r (and
 // its apply-precision copy).  Computes s = A^H r, gamma, p = s.
 template <class T>
@@ -412,10 +428,10 @@ hipError_t cgls_start(const Plan& P, const cx<double>* x, hipStream_t st, int se
     Ops<T> o{P};
     const int64_t nx = P.dim == 2 ? (int64_t)P.N * P.N : P.N;
     if (o.xbest()) hipLaunchKernelGGL(copy_kernel, dim3(nb256(nx)), dim3(256), 0, st, x, o.xbest(), nx);
-    GS_HIP_TRY(launch_apply_TH<T>(P, o.ra(), o.sa(), AFLAGS, st));
-    GS_HIP_TRY(launch_norm2<T>(o.sa(), nx, P.red, st));
+    int nred = 0;
+    GS_HIP_TRY(apply_TH_norm<T>(P, o.ra(), o.sa(), st, nred));
     hipLaunchKernelGGL((init_p_kernel<T, T>), dim3(nb256(nx)), dim3(256), 0, st, o.sa(), P.ps, o.pcopy(), nx);
-    hipLaunchKernelGGL(start_scalars_kernel, dim3(1), dim3(RT), 0, st, P.scal, P.red, set_ref, hist, hist_len);
+    hipLaunchKernelGGL(start_scalars_kernel, dim3(1), dim3(RT), 0, st, P.scal, P.red, nred, set_ref, hist, hist_len);
     return hipGetLastError();
 }
 
@@ -424,10 +440,10 @@ hipError_t cgls_iteration(const Plan& P, cx<double>* x, hipStream_t st, double* 
     Ops<T> o{P};
     const int64_t nx = P.dim == 2 ? (int64_t)P.N * P.N : P.N;
     const int64_t M = P.M;
-    GS_HIP_TRY(launch_apply_T<T>(P, o.pa(), o.qa(), AFLAGS, st));
-    GS_HIP_TRY(launch_norm2<T>(o.qa(), M, P.red, st));
+    int nq = 0, ns = 0;
+    GS_HIP_TRY(apply_T_norm<T>(P, o.pa(), o.qa(), st, nq));
     using AX = UpdateXrArgs<T, T>;
-    GS_HIP_TRY(launch_site(AX{P.scal, P.red, x, P.ps, nx, P.r, o.qa(), o.rcopy(), M},
+    GS_HIP_TRY(launch_site(AX{P.scal, P.red, nq, x, P.ps, nx, P.r, o.qa(), o.rcopy(), M},
                            [&](const AX& one, const AX* many, int count) {
                                if (many) hipLaunchKernelGGL((update_xr_kernel<T, T, true>), dim3(1024, count), dim3(RT), 0, st, one,
                                                   many);
@@ -435,23 +451,17 @@ hipError_t cgls_iteration(const Plan& P, cx<double>* x, hipStream_t st, double* 
                                                   many);
                                return hipGetLastError();
                            }));
-    GS_HIP_TRY(launch_apply_TH<T>(P, o.ra(), o.sa(), AFLAGS, st));
-    GS_HIP_TRY(launch_norm2<T>(o.sa(), nx, P.red, st));
+    GS_HIP_TRY(apply_TH_norm<T>(P, o.ra(), o.sa(), st, ns));
     using AP = UpdatePArgs<T, T>;
-    GS_HIP_TRY(launch_site(AP{P.scal, P.red, P.ps, o.sa(), o.pcopy(), nx, (const cx<double>*)x, o.xbest()},
-                           [&](const AP& one, const AP* many, int count) {
-                               if (many) hipLaunchKernelGGL((update_p_kernel<T, T, true>), dim3(256, count), dim3(RT), 0, st, one,
-                                                  many);
-        else hipLaunchKernelGGL((update_p_kernel<T, T, false>), dim3(256, count), dim3(RT), 0, st, one,
-                                                  many);
-                               return hipGetLastError();
-                           }));
-    return launch_site(StepArgs{P.scal, P.red, hist, hist_len}, [&](const StepArgs& one, const StepArgs* many,
-                                                                     int count) {
-        if (many) hipLaunchKernelGGL(step_scalars_kernel<true>, dim3(1, count), dim3(RT), 0, st, one, many);
-        else hipLaunchKernelGGL(step_scalars_kernel<false>, dim3(1, count), dim3(RT), 0, st, one, many);
-        return hipGetLastError();
-    });
+    return launch_site(AP{P.scal, P.red, ns, hist, hist_len, P.ps, o.sa(), o.pcopy(), nx, (const cx<double>*)x,
+                          o.xbest()},
+                       [&](const AP& one, const AP* many, int count) {
+                           if (many) hipLaunchKernelGGL((update_p_kernel<T, T, true>), dim3(256, count), dim3(RT), 0, st,
+                                                        one, many);
+                           else hipLaunchKernelGGL((update_p_kernel<T, T, false>), dim3(256, count), dim3(RT), 0, st,
+                                                   one, many);
+                           return hipGetLastError();
+                       });
 }
 
 // r = b - A x with applies of type T (x FP64 on device)
@@ -478,9 +488,10 @@ hipError_t cgls_run(const Plan& P, cx<double>* x, hipStream_t st, int budget, in
                     int hist_len, bool& done, bool& broke) {
     done = false;
     broke = false;
-    int it = 0;
+    int it = 0, n = std::min(check_every, budget);
+    double g_last = -1.0;
+    int it_last = 0;
     while (it < budget) {
-        const int n = std::min(check_every, budget - it);
         for (int k = 0; k < n; ++k) GS_HIP_TRY(cgls_iteration<T>(P, x, st, hist, hist_len));
         it += n;
         GS_HIP_TRY(hipMemcpyAsync(P.host_scal, P.scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -493,6 +504,22 @@ hipError_t cgls_run(const Plan& P, cx<double>* x, hipStream_t st, int budget, in
             done = true;
             return hipSuccess;
         }
+        // Iterations queued after the stop test passes run the applies for
+        // nothing, so the next batch is cut to the iteration count the
+        // observed rate of decrease of gamma predicts for reaching the
+        // tolerance (the iterates do not depend on where the checks fall).
+        int next = check_every;
+        const double g = P.host_scal[S_GAMMA], ref = P.host_scal[S_REF];
+        const double target = P.host_scal[S_TOL2] * ref * ref;
+        const int it_dev = (int)P.host_scal[S_ITER];
+        if (g_last > 0.0 && g < g_last && it_dev > it_last && target > 0.0) {
+            const double rate = std::log(g / g_last) / (it_dev - it_last);
+            const double need = std::log(target / g) / rate;
+            if (std::isfinite(need) && need < next) next = std::max(1, (int)std::ceil(need));
+        }
+        g_last = g;
+        it_last = it_dev;
+        n = std::min(next, budget - it);
     }
     return hipSuccess;
 }
@@ -518,7 +545,7 @@ int solve_setup(const Plan& P, const cx<double>* y, cx<double>* x, const gs_solv
     // reference ||A^H b|| (in apply precision T)
     if (!hipok(launch_apply_TH<T>(P, o.ra(), o.sa(), AFLAGS, st))) return GS_ERR_HIP;
     if (!hipok(launch_norm2<T>(o.sa(), nx, P.red, st))) return GS_ERR_HIP;
-    hipLaunchKernelGGL(start_scalars_kernel, dim3(1), dim3(RT), 0, st, P.scal, P.red, 1, nullptr, 0);
+    hipLaunchKernelGGL(start_scalars_kernel, dim3(1), dim3(RT), 0, st, P.scal, P.red, RB, 1, nullptr, 0);
     bool warm = opt.warm_start != 0;
     if (warm) {
         if (!hipok(compute_residual<T>(P, x, st))) return GS_ERR_HIP;

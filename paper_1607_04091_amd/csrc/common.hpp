@@ -199,10 +199,34 @@ __device__ __forceinline__ A kernel_args(const A& one, const A* __restrict__ man
     }
 }
 
+template <class T> __device__ inline double sq64(cx<T> v) {
+    const double a = (double)v.x, b = (double)v.y;
+    return a * a + b * b;
+}
+
+// Deterministic workgroup sum (fixed shuffle tree per wavefront, then the
+// wavefront sums in order); every thread gets the result
+__device__ inline double wg_sum(double v, double* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0;
+    for (int w = 0; w < nw; ++w) s += sh[w];
+    return s;
+}
+
 // launch helpers (defined in nfft.hip / fft.hip)
 template <class T> hipError_t launch_apply_T(const Plan& P, const C_t<T>* x, C_t<T>* y, int flags, hipStream_t s);
+// nsq: when non-null and norm_parts_TH(P) > 0, the adjoint also writes that
+// many FP64 partial sums of |x_k|^2 (x as stored, in a fixed order) to nsq,
+// so that ||x||^2 is their sum in index order.
 template <class T> hipError_t launch_apply_TH(const Plan& P, const C_t<T>* u, C_t<T>* x, int flags, hipStream_t s,
-                                              const Work<T>* work = nullptr);
+                                              const Work<T>* work = nullptr, double* nsq = nullptr);
+// number of partial sums launch_apply_TH writes to nsq (0: the path has none)
+int norm_parts_TH(const Plan& P);
 
 // column split of a 2D grid of side ng for the register column transform
 // (0: single-pass LDS transform, natural row order)

@@ -73,7 +73,9 @@ template <class T, class Op>
 struct FftArgs {
     Op op;
     const cx<T>* tw;
+    double* nsq;   // per-workgroup sums of the stored |value|^2, for ops whose store returns it
 };
+
 
 template <class T, int DIR, class Op>
 __device__ __forceinline__ void fft_kernel_body(const FftArgs<T, Op>& a, int n, int logn, int CB, int twstride, int ntrans) {
@@ -87,10 +89,25 @@ __device__ __forceinline__ void fft_kernel_body(const FftArgs<T, Op>& a, int n, 
         buf[c * n + bitrev(i, logn)] = (t < ntrans) ? op.load(t, i) : czero<T>();
     }
     lds_fft<T, DIR>(buf, n, logn, CB, a.tw, twstride);
-    for (int e = threadIdx.x; e < CB * n; e += blockDim.x) {
-        const int c = e % CB, k = e / CB;
-        const int t = t0 + c;
-        if (t < ntrans) op.store(t, k, buf[c * n + k]);
+    using R = decltype(op.store(0, 0, czero<T>()));
+    if constexpr (std::is_same<R, double>::value) {
+        double acc = 0;
+        for (int e = threadIdx.x; e < CB * n; e += blockDim.x) {
+            const int c = e % CB, k = e / CB;
+            const int t = t0 + c;
+            if (t < ntrans) acc += op.store(t, k, buf[c * n + k]);
+        }
+        if (a.nsq) {
+            __shared__ double sh[4];
+            const double v = wg_sum(acc, sh);
+            if (threadIdx.x == 0) a.nsq[blockIdx.x] = v;
+        }
+    } else {
+        for (int e = threadIdx.x; e < CB * n; e += blockDim.x) {
+            const int c = e % CB, k = e / CB;
+            const int t = t0 + c;
+            if (t < ntrans) op.store(t, k, buf[c * n + k]);
+        }
     }
 }
 
@@ -106,7 +123,8 @@ __global__ void __launch_bounds__(256) fft_kernel(FftArgs<T, Op> one, const FftA
 }
 
 template <class T, int DIR, class Op>
-inline hipError_t launch_fft(const Op& op, int ntrans, int n, int CB, const cx<T>* tw, int ng, hipStream_t s) {
+inline hipError_t launch_fft(const Op& op, int ntrans, int n, int CB, const cx<T>* tw, int ng, hipStream_t s,
+                             double* nsq = nullptr) {
     if (ntrans <= 0) return hipSuccess;
     const int logn = ilog2(n);
     const int blocks = (ntrans + CB - 1) / CB;
@@ -114,7 +132,7 @@ inline hipError_t launch_fft(const Op& op, int ntrans, int n, int CB, const cx<T
     int threads = CB * n / 2;
     threads = threads < 64 ? 64 : (threads > 256 ? 256 : threads);
     using A = FftArgs<T, Op>;
-    return launch_site(A{op, tw}, [&](const A& one, const A* many, int count) {
+    return launch_site(A{op, tw, nsq}, [&](const A& one, const A* many, int count) {
         if (many) hipLaunchKernelGGL((fft_kernel<T, DIR, Op, true>), dim3(blocks, count), dim3(threads), sh, s, one, many, n, logn, CB,
                            ng / n, ntrans);
         else hipLaunchKernelGGL((fft_kernel<T, DIR, Op, false>), dim3(blocks, count), dim3(threads), sh, s, one, many, n, logn, CB,
@@ -300,9 +318,9 @@ struct OpJoin {
     B b;
     int na;
     __device__ cx<T> load(int t, int i) const { return t < na ? a.load(t, i) : b.load(t - na, i); }
-    __device__ void store(int t, int k, cx<T> v) const {
-        if (t < na) a.store(t, k, v);
-        else b.store(t - na, k, v);
+    __device__ auto store(int t, int k, cx<T> v) const {
+        if (t < na) return a.store(t, k, v);
+        return b.store(t - na, k, v);
     }
 };
 

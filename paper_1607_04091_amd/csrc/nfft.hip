@@ -138,31 +138,47 @@ template <class T> struct OpT2SideCols {
     __device__ void store(int c, int q, cx<T> v) const { sc[(size_t)c * ng + q] = v; }
 };
 
+// The two adjoint output ops return |stored value|^2 (0 where nothing is
+// stored), so that a launch can also sum ||x||^2.  Every entry of x is counted
+// once: the row transforms count the interior columns of every row, the
+// side-column transforms the boundary columns of the interior rows, and, with
+// `corners` set, the row transforms of the boundary rows also count the
+// corner entries (boundary row and column), which are final before the row
+// pass runs.
 template <class T> struct OpTH2Rows {
     const cx<T>* grid; const cx<T>* sr; cx<T>* X; const T* deap; int N, nb, ng;
     int cr1 = 0, cr2 = 0;   // storage order of the grid rows (see Plan::cr1)
+    int corners = 0;
     __device__ int row(int k) const { return cr1 ? cr2 * (k & (cr1 - 1)) + k / cr1 : k; }
     __device__ cx<T> load(int i, int q) const {
         if (i >= nb && i < N - nb) return grid[(size_t)row((i - (N >> 1)) & (ng - 1)) * ng + q];
         return sr[(size_t)(i < nb ? i : nb + (N - 1 - i)) * ng + q];
     }
-    __device__ void store(int i, int q, cx<T> v) const {
+    __device__ double store(int i, int q, cx<T> v) const {
         const int j = freq_of(q, ng) + (N >> 1);
-        if (j < nb || j >= N - nb) return;
+        const bool irow = i >= nb && i < N - nb;
+        if (j < nb || j >= N - nb) {
+            if (corners && !irow && j >= 0 && j < N) return sq64(X[(size_t)i * N + j]);
+            return 0.0;
+        }
         T f = deap[j];
-        if (i >= nb && i < N - nb) f *= deap[i];
-        X[(size_t)i * N + j] = cscale(v, f);
+        if (irow) f *= deap[i];
+        const cx<T> o = cscale(v, f);
+        X[(size_t)i * N + j] = o;
+        return sq64(o);
     }
 };
 
 template <class T> struct OpTH2SideCols {
     const cx<T>* sc; cx<T>* X; const T* deap; int N, nb, ng;
     __device__ cx<T> load(int c, int q) const { return sc[(size_t)c * ng + q]; }
-    __device__ void store(int c, int q, cx<T> v) const {
+    __device__ double store(int c, int q, cx<T> v) const {
         const int i = freq_of(q, ng) + (N >> 1);
-        if (i < nb || i >= N - nb) return;
+        if (i < nb || i >= N - nb) return 0.0;
         const int j = c < nb ? c : N - 1 - (c - nb);
-        X[(size_t)i * N + j] = cscale(v, deap[i]);
+        const cx<T> o = cscale(v, deap[i]);
+        X[(size_t)i * N + j] = o;
+        return sq64(o);
     }
 };
 
@@ -556,6 +572,8 @@ hipError_t dispatch_interp(const Plan& P, const Geo<T>& g, const cx<T>* x, cx<T>
         __VA_ARGS__;               \
     } while (0)
 
+int norm_parts_TH(const Plan& P) { return P.dim == 2 && P.ts == TILE ? P.N + 2 * P.nb : 0; }
+
 template <class T>
 hipError_t launch_apply_T(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hipStream_t s) {
     const PrecData<T>& d = prec<T>(P);
@@ -595,7 +613,8 @@ hipError_t launch_apply_T(const Plan& P, const cx<T>* x, cx<T>* y, int flags, hi
 }
 
 template <class T>
-hipError_t launch_apply_TH(const Plan& P, const cx<T>* u, cx<T>* x, int flags, hipStream_t s, const Work<T>* work) {
+hipError_t launch_apply_TH(const Plan& P, const cx<T>* u, cx<T>* x, int flags, hipStream_t s, const Work<T>* work,
+                           double* nsq) {
     const PrecData<T>& d = prec<T>(P);
     const Work<T> wk = work ? *work : plan_work(d);
     const Geo<T> g = make_geo<T>(P);
@@ -610,13 +629,14 @@ hipError_t launch_apply_TH(const Plan& P, const cx<T>* u, cx<T>* x, int flags, h
             GS_TIMED(K_FFT_COLS_TH, GS_HIP_TRY((launch_fft<T, +1>(OpCols<T>{wk.grid, N, nb, ng, 0}, ng, ng,
                                                                 col_batch<T>(ng), d.tw, ng, s))));
         }
-        const OpTH2Rows<T> rows{wk.grid, wk.sr, x, d.deap, N, nb, ng, P.cr1, P.cr2};
+        OpTH2Rows<T> rows{wk.grid, wk.sr, x, d.deap, N, nb, ng, P.cr1, P.cr2};
+        rows.corners = nsq != nullptr;
         if (nb) {
             using J = OpJoin<T, OpTH2Rows<T>, OpTH2SideCols<T>>;
             GS_TIMED(K_FFT_ROWS_TH, GS_HIP_TRY((launch_fft<T, +1>(J{rows, OpTH2SideCols<T>{wk.sc, x, d.deap, N, nb, ng}, N},
-                                                                N + 2 * nb, ng, 1, d.tw, ng, s))));
+                                                                N + 2 * nb, ng, 1, d.tw, ng, s, nsq))));
         } else {
-            GS_TIMED(K_FFT_ROWS_TH, GS_HIP_TRY((launch_fft<T, +1>(rows, N, ng, 1, d.tw, ng, s))));
+            GS_TIMED(K_FFT_ROWS_TH, GS_HIP_TRY((launch_fft<T, +1>(rows, N, ng, 1, d.tw, ng, s, nsq))));
         }
         return hipSuccess;
     }
@@ -687,9 +707,9 @@ hipError_t launch_apply_TH(const Plan& P, const cx<T>* u, cx<T>* x, int flags, h
 template hipError_t launch_apply_T<float>(const Plan&, const cx<float>*, cx<float>*, int, hipStream_t);
 template hipError_t launch_apply_T<double>(const Plan&, const cx<double>*, cx<double>*, int, hipStream_t);
 template hipError_t launch_apply_TH<float>(const Plan&, const cx<float>*, cx<float>*, int, hipStream_t,
-                                           const Work<float>*);
+                                           const Work<float>*, double*);
 template hipError_t launch_apply_TH<double>(const Plan&, const cx<double>*, cx<double>*, int, hipStream_t,
-                                            const Work<double>*);
+                                            const Work<double>*, double*);
 
 // partial-buffer size needed by the adjoint (elements)
 size_t adjoint_part_elems(int dim, int64_t M, int nb, int ng) {
