@@ -263,7 +263,7 @@ CNN_SOURCES = ["paper_1607_04091_amd/csrc/cnn.hip"]
 PMC_KERNELS = {
     "spread2d": ["adj_interior_kernel<float"], "boundary2d": ["adj_boundary_kernel<float"],
     "interp_bnd2d": ["interp_bnd_kernel<float"], "interp2d": ["interp_tile_kernel<float"],
-    "adj_prep": ["adj_gather_kernel<float"], "merge_tiles": ["merge_grid_kernel<float", "merge_sides_kernel<float"],
+    "adj_prep": ["adj_gather_kernel<float"], "merge_tiles": ["merge_kernel<float"],
     "cnn_conv32": ["conv32_kernel<0"],
 }
 COPY_MIB = 512
