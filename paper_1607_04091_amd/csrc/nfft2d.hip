@@ -20,9 +20,9 @@
 //     channels per cell row and split the corner products
 //     sum_m conj(ax_r ay_c) v_m among themselves as 16x16x4 MFMA steps.
 // Each tile writes its partial padded grid, side and corner sums;
-// merge_grid_kernel and merge_sides_kernel add the partials of neighbouring
-// tiles in a fixed order.  No atomics are used, and results are bitwise
-// reproducible.
+// merge_kernel adds the partials of neighbouring tiles in a fixed order (its
+// first workgroups the grid blocks, the rest the side and corner entries).
+// No atomics are used, and results are bitwise reproducible.
 #include <algorithm>
 
 #include "common.hpp"
