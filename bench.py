@@ -224,18 +224,21 @@ def batch_c4(gs, torch, dev, n_problems):
     gs.gs_solve_batch(plans, ys, rel_tol=1e-6, max_iter=2, check_every=1, n_streams=1)   # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lone = [pl.solve(y, **kw)[1] for pl, y in zip(plans, ys)]
+    lone_runs = [pl.solve(y, **kw) for pl, y in zip(plans, ys)]
     torch.cuda.synchronize()
     t_lone = time.perf_counter() - t0
+    lone = [info for _, info in lone_runs]
     res = {}
     for ns in (1, 0):
         t0 = time.perf_counter()
-        _, infos = gs.gs_solve_batch(plans, ys, n_streams=ns, **kw)
+        xs, infos = gs.gs_solve_batch(plans, ys, n_streams=ns, **kw)
         torch.cuda.synchronize()
-        res[ns] = (time.perf_counter() - t0, infos)
-    t_batch, infos = res[0]
+        res[ns] = (time.perf_counter() - t0, infos, xs)
+    t_batch, infos, xs = res[0]
+    # equal to the lone solves: iteration counts, residuals and every solution entry bit for bit
     same = all(a["iterations"] == b["iterations"] and a["rel_residual"] == b["rel_residual"]
                for a, b in zip(lone, infos))
+    same = same and all(torch.equal(xl, xb) for (xl, _), xb in zip(lone_runs, xs))
     classes = sorted({i["batch_class"] for i in infos})
     out = {"problems": n_problems, "points": int(total_m), "weights": "Voronoi areas",
            "geometry_classes": len(classes), "streams_chosen": infos[0]["batch_streams"],

@@ -202,7 +202,9 @@ int gs_solve(const gs_plan_t* plan, const void* y, void* x, const gs_solve_opts*
  * synchronization reads all stop flags; finished problems leave their class
  * (its launches are compacted when a quarter of them have finished).
  * n_streams = 0 picks the stream count (1, 2, 4, 8, capped at the class
- * count) from short timed trial rounds; otherwise 1..64.  Per problem the
+ * count) from short timed trial rounds; otherwise 1..64 are accepted and at
+ * most 8 internal streams are used (more only take turns on the hardware
+ * queues).  Per problem the
  * kernels and their arithmetic are those of gs_solve, so every result equals
  * gs_solve's bit for bit.  The internal streams wait for `stream` on entry;
  * the call returns after all work is done.  Returns GS_OK when every problem

@@ -896,7 +896,8 @@ extern "C" int gs_solve_batch(const gs_plan_t* const* plans, int count, const vo
         cls[c].weight += (double)P.M + 4.0 * P.ng * P.ng;
     }
     const int ncls = (int)cls.size();
-    const int ns_max = n_streams > 0 ? std::min(n_streams, ncls) : std::min(8, ncls);
+    // at most 8 internal streams: more than the device's hardware queues only take turns
+    const int ns_max = std::min({n_streams > 0 ? n_streams : 8, 8, ncls});
     for (int s = 0; s < ns_max; ++s) {
         hipStream_t h;
         if (hipStreamCreateWithFlags(&h, hipStreamNonBlocking) != hipSuccess) return fail(hipErrorUnknown);
