@@ -167,3 +167,32 @@ def test_mixed_below_fp32_floor_is_graceful(gs, J, p, pattern):
 
     assert objective(xh.reshape(-1)) <= objective(x_ref) * (1 + 1e-6)
     plan.destroy()
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_check_interval_does_not_change_the_result(gs, prec):
+    """Where the host checks the stop flag (every iteration, every few, or at
+    intervals the convergence rate shortens near the tolerance) changes only
+    how many queued iterations run after the stop, and those leave every
+    vector as it is: the solution and the iteration count are identical bit
+    for bit whatever check_every is."""
+    say(f"[check interval] prec={prec}")
+    J, p = 5, 4
+    pts, mu, x0 = _small_2d(J, p, "spiral")
+    T = basis.dense_T_2d(pts, J, p)
+    y = T @ x0.reshape(-1)
+    y = y + complex_noise(y.size, 1e-4 * np.linalg.norm(y) / np.sqrt(2 * y.size), 303)
+    plan = gs.gs_plan(2, J, p, pts, mu, precision=prec)
+    yd = to_dev(y, torch.complex128)
+    runs = []
+    for ce in (1, 3, 10, 64):
+        x, info = plan.solve(yd, rel_tol=1e-9, max_iter=400, refine_fp64=True, max_restarts=4, check_every=ce)
+        say(f"  check_every={ce}: iters={info['iterations']} restarts={info['restarts']}")
+        assert info["status"] == gs.GS_OK
+        runs.append((x, info))
+    x1, i1 = runs[0]
+    for x, info in runs[1:]:
+        assert info["iterations"] == i1["iterations"] and info["restarts"] == i1["restarts"]
+        assert info["rel_residual"] == i1["rel_residual"]
+        assert torch.equal(x, x1)
+    plan.destroy()
