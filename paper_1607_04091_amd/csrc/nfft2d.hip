@@ -966,17 +966,6 @@ __device__ __forceinline__ void merge_sides_kernel_body(const MergeSidesArgs<T>&
     }
 }
 
-template <class T, int W, bool BATCH>
-__global__ void __launch_bounds__(256) merge_sides_kernel(MergeSidesArgs<T> one, const MergeSidesArgs<T>* __restrict__ many,
-                                                          int nside) {
-    if constexpr (BATCH) {
-        const MergeSidesArgs<T> a = kernel_args<true>(one, many);
-        merge_sides_kernel_body<T, W>(a, nside, blockIdx.x);
-    } else {
-        merge_sides_kernel_body<T, W>(one, nside, blockIdx.x);
-    }
-}
-
 // Grid and side merges in one launch: blocks [0, ngrid) merge the grid, the
 // rest the side grids and corners.
 template <class T>
