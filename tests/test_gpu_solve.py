@@ -196,3 +196,30 @@ def test_check_interval_does_not_change_the_result(gs, prec):
         assert info["rel_residual"] == i1["rel_residual"]
         assert torch.equal(x, x1)
     plan.destroy()
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_grid_below_a_tile_solve_matches_lstsq(gs, prec):
+    """2D at J = 3: the NFFT grid (16 x 16) is narrower than a tile, so the
+    applies take the plain 2D path and the CGLS norms come from the separate
+    reduction instead of the tile path's fused partial sums.  Plain FP64 and
+    FP32-mixed solves to 1e-10 are within 1e-6 of the oracle's weighted LS
+    solution, element by element, and independent of the check interval."""
+    say(f"[grid below a tile] prec={prec}")
+    J, p = 3, 2
+    N = 1 << J
+    pts, mu, x0 = _small_2d(J, p, "jitter")
+    T = basis.dense_T_2d(pts, J, p)
+    y = T @ x0.reshape(-1)
+    y = y + complex_noise(y.size, 1e-4 * np.linalg.norm(y) / np.sqrt(2 * y.size), 304)
+    x_ref = lsq.lstsq_dense(T, y, mu).reshape(N, N)
+    plan = gs.gs_plan(2, J, p, pts, mu, precision=prec)
+    assert plan.info()["grid_n"] < 32
+    yd = to_dev(y, torch.complex128)
+    x, info = plan.solve(yd, rel_tol=1e-10, max_iter=500, refine_fp64=True, max_restarts=8)
+    say(f"  iters={info['iterations']} restarts={info['restarts']} rr64={info['rel_residual_fp64']:.2e}")
+    assert info["status"] == gs.GS_OK
+    assert_close(to_host(x), x_ref, 1e-6, "x vs oracle LS")
+    x7, info7 = plan.solve(yd, rel_tol=1e-10, max_iter=500, refine_fp64=True, max_restarts=8, check_every=7)
+    assert info7["iterations"] == info["iterations"] and torch.equal(x7, x)
+    plan.destroy()
