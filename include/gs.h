@@ -185,6 +185,27 @@ int gs_solve(const gs_plan_t* plan, const void* y, void* x, const gs_solve_opts*
              gs_solve_info* info, void* stream);
 
 /*
+ * gs_plan_batch -- the plans of many problems in one call (the batched
+ * form's set-up): out[i] = gs_plan(descs[i]...) for i = 0..count-1, every
+ * plan built on `stream`.  Each descriptor carries gs_plan's arguments with
+ * the same meaning and limits.  All or nothing: on the first failure the
+ * plans already built are destroyed, every out[i] is NULL, and that failure's
+ * status is returned.  The plans are ordinary plans: gs_solve_batch takes
+ * them, and so does every other call; free each with gs_destroy.
+ */
+typedef struct gs_plan_desc {
+    int dim;
+    int J;
+    int p;
+    int precision;
+    int64_t M;
+    const double* xi;   /* HOST, M*dim doubles */
+    const double* mu;   /* HOST, M weights, or NULL */
+} gs_plan_desc;
+
+int gs_plan_batch(gs_plan_t** out, int count, const gs_plan_desc* descs, void* stream);
+
+/*
  * gs_solve_batch -- many independent weighted LS problems (Sec. 2, Sec. 4.1),
  * each with its own plan (sizes, point sets and precisions may differ), solved
  * together.  plans[i], y[i], x[i] follow gs_solve's layouts; plans and x

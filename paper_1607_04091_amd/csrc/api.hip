@@ -303,6 +303,24 @@ int gs_plan(gs_plan_t** out, int dim, int J, int p, int64_t M, const double* xi,
     return GS_OK;
 }
 
+int gs_plan_batch(gs_plan_t** out, int count, const gs_plan_desc* descs, void* stream) {
+    if (!out || !descs || count < 1) return GS_ERR_INVALID_ARG;
+    for (int i = 0; i < count; ++i) out[i] = nullptr;
+    for (int i = 0; i < count; ++i) {
+        const gs_plan_desc& d = descs[i];
+        const int rc = gs_plan(&out[i], d.dim, d.J, d.p, d.M, d.xi, d.mu, d.precision, stream);
+        if (rc != GS_OK) {
+            for (int k = 0; k < i; ++k) {
+                gs_destroy(out[k]);
+                out[k] = nullptr;
+            }
+            out[i] = nullptr;
+            return rc;
+        }
+    }
+    return GS_OK;
+}
+
 void gs_destroy(gs_plan_t* plan) {
     if (!plan) return;
     free_plan(plan->impl);

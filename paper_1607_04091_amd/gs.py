@@ -38,7 +38,7 @@ def _wflags(weighted):
     return GS_WEIGHTED if weighted else 0
 
 EXPORTS = [
-    "gs_plan", "gs_apply_T", "gs_apply_TH", "gs_apply_TH_noalloc", "gs_solve", "gs_solve_batch", "gs_destroy", "gs_get_plan_info",
+    "gs_plan", "gs_plan_batch", "gs_apply_T", "gs_apply_TH", "gs_apply_TH_noalloc", "gs_solve", "gs_solve_batch", "gs_destroy", "gs_get_plan_info",
     "gs_get_permutation", "gs_get_channels", "gs_weval", "gs_strerror", "gs_version", "gs_filter_taps", "gs_boundary_filters",
     "gs_eval_basis_1d", "gs_profile_enable", "gs_profile_read",
     "gs_cnn_param_count", "gs_cnn_create", "gs_cnn_destroy", "gs_cnn_set_weights", "gs_cnn_get_weights",
@@ -67,6 +67,12 @@ class SolveInfo(ctypes.Structure):
                 ("warm_start_used", ctypes.c_int), ("batch_class", ctypes.c_int), ("batch_streams", ctypes.c_int)]
 
 
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("J", ctypes.c_int), ("p", ctypes.c_int), ("precision", ctypes.c_int),
+                ("M", ctypes.c_int64), ("xi", ctypes.POINTER(ctypes.c_double)),
+                ("mu", ctypes.POINTER(ctypes.c_double))]
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("J", ctypes.c_int), ("p", ctypes.c_int), ("N", ctypes.c_int),
                 ("precision", ctypes.c_int), ("M", ctypes.c_int64), ("grid_n", ctypes.c_int),
@@ -84,6 +90,7 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
     lib.gs_plan.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i64, dp, dp, i32, vp]
+    lib.gs_plan_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(PlanDesc), vp]
     lib.gs_apply_T.argtypes = [vp, vp, vp, i32, vp]
     lib.gs_apply_TH.argtypes = [vp, vp, vp, i32, vp]
     lib.gs_apply_TH_noalloc.argtypes = [vp, vp, vp, i32, vp]
@@ -269,6 +276,31 @@ def gs_plan(dim: int, J: int, p: int, xi, mu=None, precision: int = GS_F64, stre
     if rc:
         raise GSError(rc, "gs_plan")
     return Plan(h, dim, J, p, M, precision)
+
+
+def gs_plan_batch(descs, stream=None) -> list:
+    """Plans of many problems in one call (all or nothing).  descs: a sequence of
+    dicts with the keys dim, J, p, xi and optionally mu, precision (as gs_plan)."""
+    n = len(descs)
+    if n < 1:
+        raise ValueError("gs_plan_batch: no descriptors")
+    arr = (PlanDesc * n)()
+    keep = []
+    for i, d in enumerate(descs):
+        xi = np.ascontiguousarray(d["xi"], dtype=np.float64)
+        mu = d.get("mu")
+        mu_a = None if mu is None else np.ascontiguousarray(mu, dtype=np.float64)
+        if mu_a is not None and mu_a.size != xi.shape[0]:
+            raise ValueError(f"gs_plan_batch: descriptor {i}: {mu_a.size} weights for {xi.shape[0]} points")
+        keep += [xi, mu_a]
+        arr[i] = PlanDesc(d["dim"], d["J"], d["p"], d.get("precision", GS_F64), xi.shape[0], _dptr(xi),
+                          None if mu_a is None else _dptr(mu_a))
+    hs = (ctypes.c_void_p * n)()
+    rc = _lib.gs_plan_batch(hs, n, arr, ctypes.c_void_p(0) if stream is None else _stream(stream))
+    if rc:
+        raise GSError(rc, "gs_plan_batch")
+    return [Plan(ctypes.c_void_p(hs[i]), d["dim"], d["J"], d["p"], int(arr[i].M), int(arr[i].precision))
+            for i, d in enumerate(descs)]
 
 
 class Plan:

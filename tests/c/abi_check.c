@@ -42,6 +42,12 @@ int main(void) {
     CHECK(gs_plan(&plan, 3, 5, 2, 10, &xi, NULL, GS_F64, NULL) == GS_ERR_INVALID_ARG, "gs_plan rejects dim 3");
     CHECK(gs_plan(&plan, 1, 5, 9, 1, &xi, NULL, GS_F64, NULL) == GS_ERR_UNSUPPORTED, "gs_plan rejects p 9");
     CHECK(gs_apply_T(NULL, &xi, out, 0, NULL) == GS_ERR_INVALID_ARG, "gs_apply_T rejects NULL plan");
+    gs_plan_t* plans[2] = {NULL, NULL};
+    gs_plan_desc descs[2] = {{1, 5, 9, GS_F64, 1, &xi, NULL}, {1, 5, 2, GS_F64, 1, &xi, NULL}};
+    CHECK(gs_plan_batch(plans, 0, descs, NULL) == GS_ERR_INVALID_ARG, "gs_plan_batch rejects count 0");
+    CHECK(gs_plan_batch(plans, 2, NULL, NULL) == GS_ERR_INVALID_ARG, "gs_plan_batch rejects NULL descs");
+    CHECK(gs_plan_batch(plans, 2, descs, NULL) == GS_ERR_UNSUPPORTED && !plans[0] && !plans[1],
+          "gs_plan_batch fails as a whole on an unsupported descriptor");
     gs_cnn_t* cnn = NULL;
     CHECK(gs_cnn_create(&cnn, 0, 8, 1) == GS_ERR_INVALID_ARG, "gs_cnn_create rejects height 0");
     CHECK(gs_cnn_param_count() == 38016, "gs_cnn_param_count");

@@ -190,3 +190,34 @@ def test_batch_classes_of_equal_geometry(n_streams, check_every):
     _same((xs, infos), lone)
     for pl in plans:
         pl.destroy()
+
+
+def test_plan_batch_builds_the_plans_gs_plan_builds(batch):
+    """gs_plan_batch: the plans it builds are gs_plan's (their applies agree bit
+    for bit), gs_solve_batch takes them and equals the lone solves, and a
+    batch with an unsupported descriptor fails as a whole."""
+    gs, plans, ys, _ = batch
+    descs = []
+    for k, (J, p, pat, prec) in enumerate(SPECS[:4]):
+        pts, mu = _pattern(J, pat, 600 + k)
+        descs.append(dict(dim=2, J=J, p=p, xi=pts, mu=mu, precision=prec))
+    say(f"[plan batch] {len(descs)} plans")
+    built = gs.gs_plan_batch(descs)
+    try:
+        rng = np.random.default_rng(650)
+        for pl_b, pl, (J, p, pat, prec) in zip(built, plans, SPECS):
+            f64 = prec == 0
+            dt = torch.complex128 if f64 else torch.complex64
+            x = to_dev(crandn(rng, (1 << J, 1 << J)), dt)
+            assert torch.equal(pl_b.apply_T(x, f64=f64), pl.apply_T(x, f64=f64))
+            u = to_dev(crandn(rng, pl.M), dt)
+            assert torch.equal(pl_b.apply_TH(u, f64=f64), pl.apply_TH(u, f64=f64))
+        _same(gs.gs_solve_batch(built, ys[:4], rel_tol=1e-6, max_iter=400, refine_fp64=True, max_restarts=3,
+                                check_every=3, n_streams=2), _lone(gs, plans[:4], ys[:4]))
+    finally:
+        for pl in built:
+            pl.destroy()
+    bad = descs[:2] + [dict(descs[2], p=9)]
+    with pytest.raises(gs.GSError) as e:
+        gs.gs_plan_batch(bad)
+    assert e.value.code == gs.GS_ERR_UNSUPPORTED
