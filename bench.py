@@ -210,12 +210,12 @@ def batch_c4(gs, torch, dev, n_problems):
     t0 = time.time()
     with ProcessPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
         cfgs = list(ex.map(config_c4_problem, range(n_problems), ["voronoi"] * n_problems))
-    plans, ys = [], []
-    for c in cfgs:
-        pl = gs.gs_plan(2, c["J"], c["p"], c["xi"], c["mu"], precision=gs.GS_F32_MIXED)
+    plans = gs.gs_plan_batch([dict(dim=2, J=c["J"], p=c["p"], xi=c["xi"], mu=c["mu"], precision=gs.GS_F32_MIXED)
+                              for c in cfgs])
+    ys = []
+    for c, pl in zip(cfgs, plans):
         y = torch.empty(pl.M, dtype=torch.complex128, device=dev)
         pl.apply_T(torch.from_numpy(c["x0"]).to(dev), y, f64=True)
-        plans.append(pl)
         ys.append(y)
     torch.cuda.synchronize()
     total_m = sum(pl.M for pl in plans)
