@@ -552,11 +552,19 @@ def main():
     x0 = phantom_cell_averages(ellipse_phantom_params(301), J).astype(np.complex128)
     log(f"[bench] inputs: M={M} spiral points, Voronoi weights ({time.time() - t0:.1f} s)")
 
+    # init as the paper times it (the first run excluded): the first plan of the
+    # process also loads the code objects and builds the host filter tables
+    t0 = time.perf_counter()
+    plan = gs.gs_plan(2, J, p, pts, mu, precision=gs.GS_F32_MIXED)
+    torch.cuda.synchronize()
+    t_init_first = time.perf_counter() - t0
+    plan.destroy()
     t0 = time.perf_counter()
     plan = gs.gs_plan(2, J, p, pts, mu, precision=gs.GS_F32_MIXED)
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
-    log(f"[bench] plan (init, FP32+FP64 data): {t_init:.2f} s, device bytes {plan.info()['device_bytes'] / 2**20:.0f} MiB")
+    log(f"[bench] plan (init, FP32+FP64 data): {t_init:.3f} s (first in the process {t_init_first:.3f} s), "
+        f"device bytes {plan.info()['device_bytes'] / 2**20:.0f} MiB")
 
     rng = np.random.default_rng(5)
     xs = torch.from_numpy(rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))).to(dev)
@@ -697,7 +705,7 @@ def main():
                                f"({args.arms} arms, radius <= 256), Voronoi-area weights, weighted T and T^H, FP32",
                    "points": M, "coefficients": N * N, "parallelism": "single GPU"},
         "fp64_pairs_per_s": round(1000.0 / ms64, 2),
-        "init_s": round(t_init, 3),
+        "init_s": round(t_init, 3), "init_first_in_process_s": round(t_init_first, 3),
         "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()},
         "roofline": roof,
         "pair_roofline": pair_roof,
