@@ -186,12 +186,18 @@ int gs_solve(const gs_plan_t* plan, const void* y, void* x, const gs_solve_opts*
 
 /*
  * gs_plan_batch -- the plans of many problems in one call (the batched
- * form's set-up): out[i] = gs_plan(descs[i]...) for i = 0..count-1, every
- * plan built on `stream`.  Each descriptor carries gs_plan's arguments with
- * the same meaning and limits.  All or nothing: on the first failure the
- * plans already built are destroyed, every out[i] is NULL, and that failure's
- * status is returned.  The plans are ordinary plans: gs_solve_batch takes
- * them, and so does every other call; free each with gs_destroy.
+ * form's set-up; each plan is the paper's Freq2Wave set-up of Sec. 6.2, as
+ * gs_plan builds it): out[i] = gs_plan(descs[i]...) for i = 0..count-1,
+ * every plan built on `stream`.
+ *   out    HOST array of count handles (written).
+ *   count  >= 1.
+ *   descs  HOST array of count descriptors; each carries gs_plan's arguments
+ *          with the same meaning and limits (host inputs are copied).
+ * NULL out or descs, or count < 1: GS_ERR_INVALID_ARG.  All or nothing: on
+ * the first failure the plans already built are destroyed, every out[i] is
+ * NULL, and that failure's status is returned.  The plans are ordinary
+ * plans: gs_solve_batch takes them, and so does every other call; free each
+ * with gs_destroy.
  */
 typedef struct gs_plan_desc {
     int dim;
